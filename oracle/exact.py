@@ -1,0 +1,160 @@
+"""Exact reference tools on tiny lattices (test infrastructure only).
+
+These do not simulate trajectories; they work on the full probability vector
+over all 2^N configurations, which is how the paper itself obtained its
+reference equilibrium values (Sec. 3.1: the distribution is evolved to
+equilibrium with Eq. (CK_parallel in s)).  They share no code with the
+serial oracle in kmco.c or with the HIP library, so they can pin both.
+
+State encoding: configuration index i in [0, 2^N), bit (y*L + x) of i is 1
+when spin (y, x) is +1.
+"""
+import itertools
+import math
+
+import numpy as np
+
+
+def spins_of_states(L):
+    N = L * L
+    idx = np.arange(1 << N, dtype=np.int64)
+    bits = (idx[:, None] >> np.arange(N)[None, :]) & 1
+    return (2 * bits - 1).astype(np.int8)  # [2^N, N]
+
+
+def magnetisation_and_bonds(L, S=None):
+    """M = sum of spins, B = sum over right and down periodic bonds of s s'
+    (Eq. (Hamiltonian Definition) with each bond counted once)."""
+    if S is None:
+        S = spins_of_states(L)
+    s = S.reshape(-1, L, L).astype(np.int64)
+    M = s.sum(axis=(1, 2))
+    B = (s * np.roll(s, -1, axis=2)).sum(axis=(1, 2)) + \
+        (s * np.roll(s, -1, axis=1)).sum(axis=(1, 2))
+    return M, B
+
+
+def boltzmann(L, J, h, T):
+    """pi_i = exp(-H_i/T), H = -J B - h M (Eq. (equilibrium distribution))."""
+    M, B = magnetisation_and_bonds(L)
+    E = -J * B - h * M
+    a = -E / T
+    p = np.exp(a - a.max())
+    return p / p.sum(), M, B, E
+
+
+def rate(dE, T, model):
+    """Acceptance w for energy change dE: Metropolis min(1, e^{-dE/T}) or the
+    Barker/Glauber form 1/(1 + e^{dE/T}) of Eq. (Glauber_TM)."""
+    if model == 0:
+        return np.where(dE <= 0, 1.0, np.exp(-np.maximum(dE, 0.0) / T))
+    return 1.0 / (1.0 + np.exp(dE / T))
+
+
+class TickKernel:
+    """The single-site kernel of one domain, applied to probability vectors.
+
+    In one tick, a site i of the domain (n_d sites) is selected with
+    probability 1/n_d and flipped with probability w_i(sigma); otherwise the
+    configuration is unchanged (Eq. (Glauber_TM), selection probability
+    N_D/N_S = 1/n_d).  The operator acts on the column vector p in the
+    left-stochastic convention of Eq. (CK_canonical in s).
+    """
+
+    def __init__(self, L, sites, J, h, T, model=0, quantise=False):
+        S = spins_of_states(L).astype(np.float64)
+        self.N = L * L
+        self.sites = list(sites)
+        nd = len(self.sites)
+        self.flip_prob = []
+        for i in self.sites:
+            y, x = divmod(i, L)
+            nb = [((y - 1) % L) * L + x, ((y + 1) % L) * L + x,
+                  y * L + (x - 1) % L, y * L + (x + 1) % L]
+            n = S[:, nb].sum(axis=1)
+            dE = 2.0 * S[:, i] * (J * n + h)
+            w = rate(dE, T, model)
+            if quantise:
+                w = np.minimum(np.floor(w * 2.0 ** 32 + 0.5), 2.0 ** 32) / 2.0 ** 32
+            self.flip_prob.append(w / nd)
+
+    def apply(self, p, times=1):
+        idx = np.arange(1 << self.N)
+        for _ in range(times):
+            out = p.copy()
+            for i, q in zip(self.sites, self.flip_prob):
+                moved = q * p
+                out -= moved
+                out[idx ^ (1 << i)] += moved
+            p = out
+        return p
+
+    def apply_transpose(self, v, times=1):
+        """v^T T (row-vector action); used for reversibility checks."""
+        idx = np.arange(1 << self.N)
+        for _ in range(times):
+            out = v.copy()
+            for i, q in zip(self.sites, self.flip_prob):
+                out += q * (v[idx ^ (1 << i)] - v)
+            v = out
+        return v
+
+
+def checkerboard(L, B):
+    """Domains of side B in row-major order and their colours
+    2*(ty mod 2) + (tx mod 2)."""
+    NT = L // B
+    doms, cols = [], []
+    for ty in range(NT):
+        for tx in range(NT):
+            sites = [(ty * B + ly) * L + tx * B + lx
+                     for ly in range(B) for lx in range(B)]
+            doms.append(sites)
+            cols.append(2 * (ty % 2) + (tx % 2))
+    return doms, cols
+
+
+class SweepOperator:
+    """T_SEQ(Lambda) for one colour order and T_PAR, the uniform mixture over
+    all 4! colour orders (Eq. (replica detailed balance of sequential tm) and
+    Eq. (sum of sequential tms)), or the fixed palindrome ABCDDCBA."""
+
+    def __init__(self, L, B, J, h, T, model=0, NI=None, quantise=False,
+                 palindrome=False):
+        self.doms, self.cols = checkerboard(L, B)
+        self.kern = [TickKernel(L, d, J, h, T, model, quantise) for d in self.doms]
+        self.NI = NI if NI else B * B
+        self.palindrome = palindrome
+
+    def orders(self):
+        if self.palindrome:
+            return [(0, 1, 2, 3, 3, 2, 1, 0)]
+        return list(itertools.permutations(range(4)))
+
+    def seq(self, p, order):
+        for c in order:
+            for k, col in zip(self.kern, self.cols):
+                if col == c:
+                    p = k.apply(p, self.NI)
+        return p
+
+    def seq_transpose(self, v, order):
+        for c in reversed(order):
+            for k, col in zip(self.kern, self.cols):
+                if col == c:
+                    v = k.apply_transpose(v, self.NI)
+        return v
+
+    def par(self, p):
+        outs = [self.seq(p, o) for o in self.orders()]
+        return sum(outs) / len(outs)
+
+
+def perm_rank(perm):
+    """Lexicographic rank of a permutation of range(n)."""
+    rank, avail = 0, list(range(len(perm)))
+    for i, v in enumerate(perm):
+        a = avail.index(v)
+        rank += a * math.factorial(len(perm) - 1 - i)
+        avail.pop(a)
+    return rank

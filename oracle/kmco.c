@@ -1,0 +1,545 @@
+/*
+ * kmco.c -- serial CPU oracle (test infrastructure, see kmco.h).
+ *
+ * Plain serial C: one replica, one domain at a time, one tick at a time.
+ * Nothing here is blocked, fused or vectorised; every tick is drawn, tested
+ * and applied in the order the method defines.  Build with
+ * -ffp-contract=off so that the clock and score sums round as written.
+ *
+ * Readings of the paper (each is also listed in the design notes):
+ *  R1  One of the N_I "independent time steps" of a domain process
+ *      (Sec. 2.2) is one tick of the single-site kernel of Eq. (Glauber_TM):
+ *      a site of the domain is selected with probability 1/n_d and flipped
+ *      with probability w; otherwise the tick is a null (self-loop) step.
+ *      The kernel is written in n-fold-way form: with integer rates
+ *      r = round(w 2^32), a tick draws x uniform on [0, n_d 2^32); x >= R
+ *      (R = sum of the domain's rates) is a null tick, otherwise x picks a
+ *      rate class by its prefix and a member of that class.  Each site then
+ *      flips with probability r/(n_d 2^32), the printed kernel.
+ *  R2  Rates: Barker 1/(1+e^{dE/T}) as printed, or Metropolis
+ *      min(1, e^{-dE/T}).  dE = 2 s (J n + h), n = sum of the 4 neighbours;
+ *      the field h extends Eq. (Hamiltonian Definition).
+ *  R3  Domains of one colour of a 4-colour checkerboard never touch, so the
+ *      paper's remark that the order of non-interacting domains is
+ *      irrelevant (Sec. 2.2) lets the schedule be a permutation of the four
+ *      colours, drawn uniformly each sweep (w(L) = 1/4!, closed under
+ *      reversal, Eq. (sum of sequential tms)), or the self-reverse
+ *      palindrome A B C D D C B A.  Domains of a colour run in ascending
+ *      index order; they commute.
+ *  R4  Clock: the residence time of Eq. (Poisson Distribution) is drawn per
+ *      accepted event as -ln(u)/R_w with R_w = R / 2^32 the domain's total
+ *      rate before the event (the paper advances by the mean; it states both
+ *      are equivalent).  Each domain sums its own clock (compensated sum);
+ *      the replica time is the mean over domains.  The integer step count
+ *      of Eq. (CK_parallel in s) is kept as well.
+ *  R5  Score: d log P(path)/d theta for theta in (J, h) of the tick chain:
+ *      an event at class c adds d ln w_c/d theta, a null tick adds
+ *      d ln(1 - R_w/n_d)/d theta = -R'_w/(n_d - R_w), R'_w = sum_c n_c w_c g_c,
+ *      using the unquantised w.  The paper has no score; this is the
+ *      likelihood ratio of the chain it defines.
+ *  R6  Random numbers: Philox4x32-10, key = (seed low, seed high),
+ *      counter = (tick, domain | visit<<20 | stream<<24, sweep, replica).
+ *      Word 1 gives the slot (Lemire multiply with rejection, retried on
+ *      streams 3..14), word 0 the low 32 bits of x, words 3:2 the 53-bit
+ *      uniform for the clock.
+ */
+#include "kmco.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define STREAM_TICK 0u
+#define STREAM_INIT 1u
+#define STREAM_SCHED 2u
+#define STREAM_RETRY0 3u
+#define MAX_RETRY 12
+
+/* ---------------------------------------------------------------- Philox */
+
+void kmco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    /* Philox4x32: per round two 32x32->64 products of counter words 0 and 2
+     * with the multipliers; the high halves are mixed with words 1, 3 and the
+     * round key, the low halves pass through.  The key advances by the Weyl
+     * constants between rounds. */
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                 uint32_t c3, uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    kmco_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------ rate table */
+
+int kmco_rates(double J, double h, double T, int32_t model,
+               uint64_t r[10], double w[10], double gJ[10], double gh[10])
+{
+    if (!(T > 0.0) || !isfinite(T) || !isfinite(J) || !isfinite(h)) return -1;
+    if (model != KMCO_METROPOLIS && model != KMCO_BARKER) return -1;
+    for (int c = 0; c < 10; ++c) {
+        int up = c / 5;                 /* 1 if the site spin is +1      */
+        int k = c % 5;                  /* number of up neighbours       */
+        double s = up ? 1.0 : -1.0;
+        double n = (double)(2 * k - 4); /* neighbour sum                 */
+        double dE = 2.0 * s * (J * n + h);
+        double dEdJ = 2.0 * s * n;
+        double dEdh = 2.0 * s;
+        double wc, dlogw_ddE;
+        if (model == KMCO_METROPOLIS) {
+            if (dE <= 0.0) {
+                wc = 1.0;
+                dlogw_ddE = 0.0;
+            } else {
+                wc = exp(-dE / T);
+                dlogw_ddE = -1.0 / T;
+            }
+        } else {
+            wc = 1.0 / (1.0 + exp(dE / T));
+            dlogw_ddE = -(1.0 - wc) / T;
+        }
+        double q = floor(wc * 4294967296.0 + 0.5);
+        if (q > 4294967296.0) q = 4294967296.0;
+        r[c] = (uint64_t)q;
+        w[c] = wc;
+        gJ[c] = dlogw_ddE * dEdJ;
+        gh[c] = dlogw_ddE * dEdh;
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------------- schedule */
+
+void kmco_perm_from_index(int32_t idx, int32_t perm[4])
+{
+    /* lexicographic rank -> permutation of {0,1,2,3} */
+    int avail[4] = {0, 1, 2, 3};
+    int navail = 4;
+    int radix[3] = {6, 2, 1};
+    for (int i = 0; i < 3; ++i) {
+        int a = idx / radix[i];
+        idx %= radix[i];
+        perm[i] = avail[a];
+        for (int j = a; j < navail - 1; ++j) avail[j] = avail[j + 1];
+        --navail;
+    }
+    perm[3] = avail[0];
+}
+
+int32_t kmco_schedule_index(uint64_t seed, int32_t replica, int64_t sweep)
+{
+    /* Uniform on [0,24): Lemire multiply-high with rejection of the
+     * (2^32 mod 24) = 16 smallest low halves, words taken in order. */
+    for (uint32_t call = 0;; ++call) {
+        uint32_t o[4];
+        draw(seed, call, STREAM_SCHED << 24, (uint32_t)sweep,
+             (uint32_t)replica, o);
+        for (int i = 0; i < 4; ++i) {
+            uint64_t m = (uint64_t)o[i] * 24u;
+            if ((uint32_t)m >= 16u) return (int32_t)(m >> 32);
+        }
+    }
+}
+
+uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
+                        int32_t domain, int32_t visit, uint32_t tick,
+                        uint32_t n, int32_t *retries)
+{
+    uint32_t thr = (uint32_t)(0u - n) % n;  /* 2^32 mod n */
+    uint32_t word1;
+    uint32_t o[4];
+    uint32_t c1 = (uint32_t)domain | ((uint32_t)visit << 20);
+    draw(seed, tick, c1 | (STREAM_TICK << 24), (uint32_t)sweep,
+         (uint32_t)replica, o);
+    word1 = o[1];
+    int k = 0;
+    for (;;) {
+        uint64_t m = (uint64_t)word1 * n;
+        if ((uint32_t)m >= thr || k == MAX_RETRY) {
+            if (retries) *retries = k;
+            return (uint32_t)(m >> 32);
+        }
+        ++k;
+        draw(seed, tick, c1 | ((STREAM_RETRY0 + (uint32_t)(k - 1)) << 24),
+             (uint32_t)sweep, (uint32_t)replica, o);
+        word1 = o[1];
+    }
+}
+
+/* ---------------------------------------------------------------- state */
+
+struct kmco_state {
+    int L, B, NT, ND, nd, NI, sched, model;
+    double J, h, T;
+    uint64_t seed;
+    int replica;
+    int8_t *spin;          /* L*L, row-major, +1 / -1                     */
+    uint64_t r[10];
+    double w[10], gJ[10], gh[10];
+    double *clk_sum, *clk_comp; /* per domain                             */
+    int64_t *dom_events;
+    int64_t sweep, events, steps;
+    /* per-visit scratch */
+    int nw;                /* words per class bitset                      */
+    uint64_t *bits;        /* [10][nw]                                    */
+    int8_t *cls;           /* [nd]                                        */
+    int64_t check_fail;
+};
+
+static inline int wrap(int a, int L) { a %= L; return a < 0 ? a + L : a; }
+
+static inline int8_t spin_at(const kmco_state *s, int y, int x)
+{
+    return s->spin[wrap(y, s->L) * s->L + wrap(x, s->L)];
+}
+
+/* Class of lattice site (y, x): 5*[spin up] + number of up neighbours. */
+static int site_class(const kmco_state *s, int y, int x)
+{
+    int up = spin_at(s, y, x) > 0;
+    int k = (spin_at(s, y - 1, x) > 0) + (spin_at(s, y + 1, x) > 0) +
+            (spin_at(s, y, x - 1) > 0) + (spin_at(s, y, x + 1) > 0);
+    return 5 * up + k;
+}
+
+kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
+                        const int8_t *given)
+{
+    if (!d || d->L < 1 || d->tile < 1 || d->L % d->tile) return NULL;
+    int NT = d->L / d->tile;
+    if (NT > 1 && NT % 2) return NULL; /* 4-colour checkerboard needs even NT */
+    if (d->steps_per_visit < 0) return NULL;
+    if (d->schedule != KMCO_SCHED_RANDOM_PERM &&
+        d->schedule != KMCO_SCHED_PALINDROME) return NULL;
+    kmco_state *s = (kmco_state *)calloc(1, sizeof(*s));
+    if (!s) return NULL;
+    s->L = d->L; s->B = d->tile; s->NT = NT; s->ND = NT * NT;
+    s->nd = d->tile * d->tile;
+    s->NI = d->steps_per_visit ? d->steps_per_visit : s->nd;
+    s->sched = d->schedule; s->model = d->rate_model;
+    s->J = d->J; s->h = d->h; s->T = d->T;
+    s->seed = seed; s->replica = replica;
+    if (kmco_rates(s->J, s->h, s->T, s->model, s->r, s->w, s->gJ, s->gh)) {
+        free(s);
+        return NULL;
+    }
+    size_t N = (size_t)s->L * s->L;
+    s->spin = (int8_t *)malloc(N);
+    s->clk_sum = (double *)calloc(s->ND, sizeof(double));
+    s->clk_comp = (double *)calloc(s->ND, sizeof(double));
+    s->dom_events = (int64_t *)calloc(s->ND, sizeof(int64_t));
+    s->nw = (s->nd + 63) / 64;
+    s->bits = (uint64_t *)calloc((size_t)10 * s->nw, sizeof(uint64_t));
+    s->cls = (int8_t *)malloc(s->nd);
+    if (!s->spin || !s->clk_sum || !s->clk_comp || !s->dom_events ||
+        !s->bits || !s->cls) {
+        kmco_destroy(s);
+        return NULL;
+    }
+    for (size_t i = 0; i < N; ++i) {
+        if (d->init == KMCO_INIT_ALL_UP) {
+            s->spin[i] = 1;
+        } else if (d->init == KMCO_INIT_GIVEN) {
+            if (!given || (given[i] != 1 && given[i] != -1)) {
+                kmco_destroy(s);
+                return NULL;
+            }
+            s->spin[i] = given[i];
+        } else {
+            /* bit i of the INIT stream: call i/128, word (i/32)%4, bit i%32 */
+            uint32_t o[4];
+            draw(seed, (uint32_t)(i >> 7), STREAM_INIT << 24, 0u,
+                 (uint32_t)replica, o);
+            uint32_t bit = (o[(i >> 5) & 3] >> (i & 31)) & 1u;
+            s->spin[i] = bit ? 1 : -1;
+        }
+    }
+    return s;
+}
+
+void kmco_destroy(kmco_state *s)
+{
+    if (!s) return;
+    free(s->spin); free(s->clk_sum); free(s->clk_comp); free(s->dom_events);
+    free(s->bits); free(s->cls);
+    free(s);
+}
+
+/* -------------------------------------------------------- domain process */
+
+static void set_class(kmco_state *s, int k, int c, int64_t n[10])
+{
+    s->cls[k] = (int8_t)c;
+    s->bits[(size_t)c * s->nw + (k >> 6)] |= (uint64_t)1 << (k & 63);
+    n[c] += 1;
+}
+
+static void clear_class(kmco_state *s, int k, int64_t n[10])
+{
+    int c = s->cls[k];
+    s->bits[(size_t)c * s->nw + (k >> 6)] &= ~((uint64_t)1 << (k & 63));
+    n[c] -= 1;
+}
+
+/* Local index of the j-th member (0-based, ascending local index) of class c. */
+static int select_member(const kmco_state *s, int c, uint64_t j)
+{
+    const uint64_t *b = s->bits + (size_t)c * s->nw;
+    for (int q = 0; q < s->nw; ++q) {
+        uint64_t cnt = (uint64_t)__builtin_popcountll(b[q]);
+        if (j < cnt) {
+            uint64_t word = b[q];
+            for (int bit = 0; bit < 64; ++bit) {
+                if ((word >> bit) & 1u) {
+                    if (j == 0) return q * 64 + bit;
+                    --j;
+                }
+            }
+        }
+        j -= cnt;
+    }
+    return -1;
+}
+
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x))
+        *comp += (*sum - t) + x;
+    else
+        *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+/* nu_theta = d ln(1 - R_w/n_d)/d theta for the current class counts. */
+static void null_score(const kmco_state *s, const int64_t n[10], double nu[2])
+{
+    double Rw = 0.0, RJ = 0.0, Rh = 0.0;
+    for (int c = 0; c < 10; ++c) {
+        double nc = (double)n[c];
+        Rw += nc * s->w[c];
+        RJ += nc * (s->w[c] * s->gJ[c]);
+        Rh += nc * (s->w[c] * s->gh[c]);
+    }
+    double den = (double)s->nd - Rw;
+    if (den > 0.0) {
+        nu[0] = -RJ / den;
+        nu[1] = -Rh / den;
+    } else {
+        nu[0] = 0.0;
+        nu[1] = 0.0;
+    }
+}
+
+static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
+{
+    int64_t cnt[10] = {0};
+    for (int k = 0; k < s->nd; ++k) {
+        int c = site_class(s, oy + k / s->B, ox + k % s->B);
+        cnt[c]++;
+        if (c != s->cls[k]) s->check_fail++;
+        if (!((s->bits[(size_t)c * s->nw + (k >> 6)] >> (k & 63)) & 1u))
+            s->check_fail++;
+    }
+    for (int c = 0; c < 10; ++c)
+        if (cnt[c] != n[c]) s->check_fail++;
+}
+
+/* Runs one domain process: N_I ticks of domain d with everything outside the
+ * domain held fixed (the halo is read from the lattice, which no other
+ * domain changes during the visit). */
+static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
+                         int flags, double *score)
+{
+    const int B = s->B, L = s->L;
+    const int oy = (d / s->NT) * B, ox = (d % s->NT) * B;
+    int64_t n[10] = {0};
+    memset(s->bits, 0, sizeof(uint64_t) * 10 * (size_t)s->nw);
+    for (int k = 0; k < s->nd; ++k)
+        set_class(s, k, site_class(s, oy + k / B, ox + k % B), n);
+
+    uint64_t m_null = 0; /* null ticks since the last event (score) */
+    for (int t = 0; t < s->NI; ++t) {
+        uint64_t R = 0;
+        for (int c = 0; c < 10; ++c) R += (uint64_t)n[c] * s->r[c];
+
+        uint32_t o[4];
+        draw(s->seed, (uint32_t)t,
+             (uint32_t)d | ((uint32_t)visit << 20) | (STREAM_TICK << 24),
+             (uint32_t)w, (uint32_t)s->replica, o);
+        uint32_t slot = kmco_tick_slot(s->seed, s->replica, w, d, visit,
+                                       (uint32_t)t, (uint32_t)s->nd, NULL);
+        uint64_t x = ((uint64_t)slot << 32) | o[0];
+        if (x >= R) { /* null tick: the selected site is not flipped */
+            ++m_null;
+            continue;
+        }
+        /* event: rate class by prefix, then member j of that class */
+        int c = 0;
+        uint64_t P = 0;
+        while (x >= P + (uint64_t)n[c] * s->r[c]) {
+            P += (uint64_t)n[c] * s->r[c];
+            ++c;
+        }
+        uint64_t j = (x - P) / s->r[c];
+        int k = select_member(s, c, j);
+        int ly = k / B, lx = k % B;
+        int gy = oy + ly, gx = ox + lx;
+
+        if (flags & KMCO_F_SCORE) {
+            if (m_null) {
+                double nu[2];
+                null_score(s, n, nu);
+                score[0] += (double)m_null * nu[0];
+                score[1] += (double)m_null * nu[1];
+            }
+            score[0] += s->gJ[c];
+            score[1] += s->gh[c];
+        }
+        m_null = 0;
+
+        /* residence time -ln(u)/R_w, u in (0, 1] from 53 bits of words 3:2 */
+        uint64_t u53 = ((uint64_t)o[3] << 21) | (o[2] >> 11);
+        double u = (double)(u53 + 1) * 0x1p-53;
+        double dt = -log(u) * 4294967296.0 / (double)R;
+        neumaier_add(&s->clk_sum[d], &s->clk_comp[d], dt);
+
+        /* the flipped site and its neighbours inside the domain change class */
+        int aff[5], na = 0;
+        const int dy[5] = {0, -1, 1, 0, 0}, dx[5] = {0, 0, 0, -1, 1};
+        for (int a = 0; a < 5; ++a) {
+            int yy = wrap(gy + dy[a], L), xx = wrap(gx + dx[a], L);
+            int ry = wrap(yy - oy, L), rx = wrap(xx - ox, L);
+            if (ry >= B || rx >= B) continue; /* halo site: frozen */
+            int kk = ry * B + rx, dup = 0;
+            for (int b = 0; b < na; ++b) dup |= aff[b] == kk;
+            if (!dup) aff[na++] = kk;
+        }
+        for (int a = 0; a < na; ++a) clear_class(s, aff[a], n);
+        s->spin[gy * L + gx] = (int8_t)-s->spin[gy * L + gx];
+        for (int a = 0; a < na; ++a)
+            set_class(s, aff[a],
+                      site_class(s, oy + aff[a] / B, ox + aff[a] % B), n);
+        s->events++;
+        s->dom_events[d]++;
+        if (flags & KMCO_F_CHECK) check_classes(s, oy, ox, n);
+    }
+    if ((flags & KMCO_F_SCORE) && m_null) {
+        double nu[2];
+        null_score(s, n, nu);
+        score[0] += (double)m_null * nu[0];
+        score[1] += (double)m_null * nu[1];
+    }
+    s->steps += s->NI;
+}
+
+static void observe(const kmco_state *s, kmco_record *r)
+{
+    int64_t M = 0, Bs = 0;
+    for (int y = 0; y < s->L; ++y)
+        for (int x = 0; x < s->L; ++x) {
+            int8_t v = spin_at(s, y, x);
+            M += v;
+            Bs += v * (spin_at(s, y, x + 1) + spin_at(s, y + 1, x));
+        }
+    double tot = 0.0;
+    for (int d = 0; d < s->ND; ++d) tot += s->clk_sum[d] + s->clk_comp[d];
+    r->sweep = s->sweep;
+    r->M = M;
+    r->B = Bs;
+    r->events = s->events;
+    r->steps = s->steps;
+    r->t = tot / (double)s->ND;
+}
+
+int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
+                 int32_t flags, kmco_record *rec, int64_t rec_cap,
+                 double *score)
+{
+    if (!s || n_sweeps < 0 || record_every < 1) return -1;
+    if ((flags & KMCO_F_SCORE) && !score) return -1;
+    static const int pal[8] = {0, 1, 2, 3, 3, 2, 1, 0};
+    int64_t nrec = 0;
+    double dummy[2];
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const int64_t w = s->sweep;
+        int order[8], visit[8], nphase;
+        if (s->sched == KMCO_SCHED_PALINDROME) {
+            nphase = 8;
+            for (int p = 0; p < 8; ++p) {
+                order[p] = pal[p];
+                visit[p] = p < 4 ? 0 : 1;
+            }
+        } else {
+            int32_t perm[4];
+            kmco_perm_from_index(kmco_schedule_index(s->seed, s->replica, w),
+                                 perm);
+            nphase = 4;
+            for (int p = 0; p < 4; ++p) {
+                order[p] = perm[p];
+                visit[p] = 0;
+            }
+        }
+        double *sc = (flags & KMCO_F_SCORE)
+                         ? (nrec < rec_cap ? score + 2 * nrec : dummy)
+                         : NULL;
+        for (int p = 0; p < nphase; ++p) {
+            for (int d = 0; d < s->ND; ++d) {
+                int ty = d / s->NT, tx = d % s->NT;
+                int colour = 2 * (ty & 1) + (tx & 1);
+                if (colour == order[p])
+                    visit_domain(s, d, visit[p], w, flags, sc);
+            }
+        }
+        s->sweep++;
+        if ((i + 1) % record_every == 0) {
+            if (nrec < rec_cap && rec) observe(s, &rec[nrec]);
+            ++nrec;
+        }
+    }
+    return nrec;
+}
+
+int kmco_get_spins(const kmco_state *s, int8_t *out)
+{
+    if (!s || !out) return -1;
+    memcpy(out, s->spin, (size_t)s->L * s->L);
+    return 0;
+}
+
+int kmco_get_domain_clocks(const kmco_state *s, double *sum, double *comp)
+{
+    if (!s) return -1;
+    if (sum) memcpy(sum, s->clk_sum, sizeof(double) * s->ND);
+    if (comp) memcpy(comp, s->clk_comp, sizeof(double) * s->ND);
+    return 0;
+}
+
+int kmco_get_domain_events(const kmco_state *s, int64_t *events)
+{
+    if (!s || !events) return -1;
+    memcpy(events, s->dom_events, sizeof(int64_t) * s->ND);
+    return 0;
+}
+
+int64_t kmco_check_failures(const kmco_state *s) { return s ? s->check_fail : -1; }

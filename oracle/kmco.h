@@ -1,0 +1,98 @@
+/*
+ * kmco.h -- serial CPU oracle for domain-decomposed sequential-update kMC.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library and its Python binding) never calls it, and the two share
+ * no code: the Philox generator, the rate table, the schedule draw, the
+ * event selection and the clocks are all written out again here.
+ *
+ * What it computes (Nilmeier & Marian, "A rigorous sequential update strategy
+ * for parallel kinetic Monte Carlo simulation"):
+ *   - periodic 2D Ising energy, Appendix A, Eq. (Hamiltonian Definition),
+ *     extended by a uniform field h:  H = -J sum_<ij> s_i s_j - h sum_i s_i;
+ *   - single-site kernel with self-loops, Appendix A, Eq. (Glauber_TM):
+ *     selection probability 1/n_d inside a domain, acceptance w (Barker form
+ *     as printed, or Metropolis min(1, exp(-dE/T)));
+ *   - equal, fixed domains with a frozen halo, each run for N_I steps,
+ *     Sec. 2.2 and Fig. 1;
+ *   - a schedule drawn uniformly each sweep, Eq. (schedule) and
+ *     Eq. (sum of sequential tms); non-interacting domains (one colour of a
+ *     4-colour checkerboard) run in one phase, Sec. 2.2;
+ *   - n-fold-way residence time tau = 1/R per event, Eq. (Poisson
+ *     Distribution) and the text after it;
+ *   - integer step count s += N_I * N_D per sweep, Eq. (CK_parallel in s);
+ *   - statistics only at domain-process endpoints (sweep ends), Sec. 2.3.
+ * The readings taken where the paper is silent are listed in the header
+ * comment of kmco.c.
+ */
+#ifndef KMCO_H
+#define KMCO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { KMCO_METROPOLIS = 0, KMCO_BARKER = 1 };
+enum { KMCO_SCHED_RANDOM_PERM = 0, KMCO_SCHED_PALINDROME = 1 };
+enum { KMCO_INIT_RANDOM = 0, KMCO_INIT_ALL_UP = 1, KMCO_INIT_GIVEN = 2 };
+enum { KMCO_F_SCORE = 1, KMCO_F_CHECK = 2 };
+
+typedef struct {
+    double J, h, T;
+    int32_t L;               /* periodic L x L lattice                    */
+    int32_t tile;            /* B: square domain side, L % B == 0          */
+    int32_t steps_per_visit; /* N_I ticks per domain visit; 0 means B*B    */
+    int32_t rate_model;      /* KMCO_METROPOLIS or KMCO_BARKER             */
+    int32_t schedule;        /* KMCO_SCHED_*                                */
+    int32_t init;            /* KMCO_INIT_*                                 */
+} kmco_desc;
+
+typedef struct {
+    int64_t sweep;   /* sweeps completed since creation                   */
+    int64_t M;       /* sum of spins                                      */
+    int64_t B;       /* sum over right and down bonds of s_i s_j          */
+    int64_t events;  /* accepted flips since creation                     */
+    int64_t steps;   /* ticks since creation (N_I per visit)              */
+    double  t;       /* mean over domains of the per-domain event clocks  */
+} kmco_record;
+
+typedef struct kmco_state kmco_state;
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void kmco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Per-class rate table: class c = 5*[s=+1] + k, k = up-neighbour count. */
+int kmco_rates(double J, double h, double T, int32_t model,
+               uint64_t r[10], double w[10], double gJ[10], double gh[10]);
+
+/* Index in [0,24) of the colour permutation for (seed, replica, sweep). */
+int32_t kmco_schedule_index(uint64_t seed, int32_t replica, int64_t sweep);
+void kmco_perm_from_index(int32_t idx, int32_t perm[4]);
+
+/* Uniform slot in [0, n) for one tick, with rejection and retries. */
+uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
+                        int32_t domain, int32_t visit, uint32_t tick,
+                        uint32_t n, int32_t *retries);
+
+kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
+                        const int8_t *given);
+/* Runs n_sweeps sweeps.  After the i-th sweep of this call (1-based) a record
+ * is written when i % record_every == 0.  With KMCO_F_SCORE the likelihood-
+ * ratio score (d/dJ, d/dh) of every tick is added to score[2*k], score[2*k+1]
+ * where k is the record that closes the interval holding the tick.
+ * Returns the number of records written, or a negative error code. */
+int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
+                 int32_t flags, kmco_record *rec, int64_t rec_cap,
+                 double *score);
+int kmco_get_spins(const kmco_state *s, int8_t *out);
+int kmco_get_domain_clocks(const kmco_state *s, double *sum, double *comp);
+int kmco_get_domain_events(const kmco_state *s, int64_t *events);
+int64_t kmco_check_failures(const kmco_state *s);
+void kmco_destroy(kmco_state *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

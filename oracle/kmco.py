@@ -1,0 +1,160 @@
+"""ctypes wrapper of the serial C oracle (test infrastructure only).
+
+The wrapper only marshals arguments; every step of the method runs in kmco.c.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+METROPOLIS, BARKER = 0, 1
+SCHED_RANDOM_PERM, SCHED_PALINDROME = 0, 1
+INIT_RANDOM, INIT_ALL_UP, INIT_GIVEN = 0, 1, 2
+F_SCORE, F_CHECK = 1, 2
+
+
+class Desc(C.Structure):
+    _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
+                ("L", C.c_int32), ("tile", C.c_int32),
+                ("steps_per_visit", C.c_int32), ("rate_model", C.c_int32),
+                ("schedule", C.c_int32), ("init", C.c_int32)]
+
+
+class Record(C.Structure):
+    _fields_ = [("sweep", C.c_int64), ("M", C.c_int64), ("B", C.c_int64),
+                ("events", C.c_int64), ("steps", C.c_int64), ("t", C.c_double)]
+
+
+RECORD_DTYPE = np.dtype([("sweep", "<i8"), ("M", "<i8"), ("B", "<i8"),
+                         ("events", "<i8"), ("steps", "<i8"), ("t", "<f8")])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        P = C.c_void_p
+        L.kmco_philox.argtypes = [P, P, P]
+        L.kmco_rates.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32,
+                                 P, P, P, P]
+        L.kmco_schedule_index.argtypes = [C.c_uint64, C.c_int32, C.c_int64]
+        L.kmco_schedule_index.restype = C.c_int32
+        L.kmco_perm_from_index.argtypes = [C.c_int32, P]
+        L.kmco_tick_slot.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32,
+                                     C.c_int32, C.c_uint32, C.c_uint32, P]
+        L.kmco_tick_slot.restype = C.c_uint32
+        L.kmco_create.argtypes = [C.POINTER(Desc), C.c_uint64, C.c_int32, P]
+        L.kmco_create.restype = P
+        L.kmco_run.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P]
+        L.kmco_run.restype = C.c_int64
+        L.kmco_get_spins.argtypes = [P, P]
+        L.kmco_get_domain_clocks.argtypes = [P, P, P]
+        L.kmco_get_domain_events.argtypes = [P, P]
+        L.kmco_check_failures.argtypes = [P]
+        L.kmco_check_failures.restype = C.c_int64
+        L.kmco_destroy.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().kmco_philox(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def rates(J, h, T, model=METROPOLIS):
+    r = np.zeros(10, np.uint64)
+    w, gJ, gh = (np.zeros(10) for _ in range(3))
+    if lib().kmco_rates(J, h, T, model, _ptr(r), _ptr(w), _ptr(gJ), _ptr(gh)):
+        raise ValueError("invalid rate parameters")
+    return r, w, gJ, gh
+
+
+def schedule_index(seed, replica, sweep):
+    return lib().kmco_schedule_index(seed, replica, sweep)
+
+
+def perm_from_index(idx):
+    p = np.zeros(4, np.int32)
+    lib().kmco_perm_from_index(idx, _ptr(p))
+    return p
+
+
+def tick_slot(seed, replica, sweep, domain, visit, tick, n):
+    r = C.c_int32(0)
+    v = lib().kmco_tick_slot(seed, replica, sweep, domain, visit, tick, n,
+                             C.byref(r))
+    return v, r.value
+
+
+class Replica:
+    """One replica of the oracle: lattice, clocks and counters."""
+
+    def __init__(self, L, tile, J=1.0, h=0.0, T=2.5, steps_per_visit=0,
+                 rate_model=METROPOLIS, schedule=SCHED_RANDOM_PERM,
+                 init=INIT_RANDOM, seed=1, replica=0, spins=None):
+        self.desc = Desc(J, h, T, L, tile, steps_per_visit, rate_model,
+                         schedule, init)
+        self.L, self.tile = L, tile
+        self.nd = tile * tile
+        self.ND = (L // tile) ** 2
+        self.NI = steps_per_visit or self.nd
+        given = None
+        if spins is not None:
+            self._given = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+            given = _ptr(self._given)
+        self._h = lib().kmco_create(C.byref(self.desc), seed, replica, given)
+        if not self._h:
+            raise ValueError("oracle rejected the replica description")
+
+    def run(self, n_sweeps, record_every=1, score=False, check=False):
+        cap = -(-n_sweeps // record_every) if n_sweeps else 0
+        rec = np.zeros(max(cap, 1), RECORD_DTYPE)
+        sc = np.zeros((max(cap, 1), 2))
+        flags = (F_SCORE if score else 0) | (F_CHECK if check else 0)
+        n = lib().kmco_run(self._h, n_sweeps, record_every, flags, _ptr(rec), cap,
+                           _ptr(sc))
+        if n < 0:
+            raise ValueError("oracle run failed")
+        if score:
+            return rec[:n], sc[:cap]
+        return rec[:n]
+
+    def spins(self):
+        out = np.zeros((self.L, self.L), np.int8)
+        lib().kmco_get_spins(self._h, _ptr(out))
+        return out
+
+    def domain_clocks(self):
+        s = np.zeros(self.ND)
+        c = np.zeros(self.ND)
+        lib().kmco_get_domain_clocks(self._h, _ptr(s), _ptr(c))
+        return s, c
+
+    def domain_events(self):
+        e = np.zeros(self.ND, np.int64)
+        lib().kmco_get_domain_events(self._h, _ptr(e))
+        return e
+
+    def check_failures(self):
+        return lib().kmco_check_failures(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().kmco_destroy(h)
+            self._h = None
