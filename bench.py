@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the domain-decomposed sequential-update kMC hot path.
+
+One step = one schedule sweep of the 1024x1024 periodic Ising lattice cut
+into 32x32 domains (1024 domains, 4 colour phases of 256 concurrent domain
+processes, N_I = 1024 ticks per visit, Metropolis, T = 2.269, random start):
+every domain visit, class bookkeeping, event selection, clock and the sweep
+record.  value = site updates (ticks, null ticks included) per second.
+
+Extra measurements on the same line: the batched persistent form
+(4096 ragged replicas), the backward score replay overhead (1024 replicas of
+64x64), the roofline of the dominant kernel and the serial CPU oracle on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Integer lane-operations per tick and per event that the method itself
+# requires (see the design notes): one Philox4x32-10 call per tick (20
+# 32x32->64 products = 40 multiplies, 40 XORs, 18 key additions) plus the
+# slot and 64-bit threshold test; per event the class prefix, the member
+# rank, five reclassifications and the count / rate-sum update.
+OPS_PER_TICK = 102
+OPS_PER_EVENT = 64
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer lane-operations/s
+ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def timed(fn, stream):
+    import torch
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3
+
+
+def plain(args, kmc, workloads):
+    import torch
+    seed, descs, _ = workloads.single_1024(2.269)
+    d = descs[0]
+    lat = kmc.Lattice(descs, seed)
+    stream = torch.cuda.current_stream()
+    flags = kmc.F_GRAPH if args.graph else 0
+    lat.run(args.warmup, 1, flags)
+    torch.cuda.synchronize()
+    ev0 = lat.records()[0][-1]["events"] if args.warmup else 0
+    sec = timed(lambda: lat.run(args.steps, 1, flags), stream)
+    rec = lat.records()[0]
+    events = int(rec[-1]["events"] - ev0)
+    ticks = args.steps * d["L"] ** 2
+    lat.close()
+    return dict(sec=sec, ticks=ticks, events=events, launches=4 * args.steps,
+                desc=d, seed=seed)
+
+
+def batched(args, kmc, workloads):
+    import torch
+    seed, descs, _ = workloads.batched_4096()
+    lat = kmc.Lattice(descs, seed)
+    stream = torch.cuda.current_stream()
+    lat.run(2, 1, kmc.F_PERSISTENT)
+    sec = timed(lambda: lat.run(args.batched_sweeps, args.batched_sweeps,
+                                kmc.F_PERSISTENT), stream)
+    ticks = args.batched_sweeps * sum(x["L"] ** 2 for x in descs)
+    lat.close()
+    return dict(sec=sec, ticks=ticks, replicas=len(descs), sweeps=args.batched_sweeps)
+
+
+def backward(args, kmc, workloads):
+    import torch
+    seed, descs, _ = workloads.differentiable_1024()
+    n = args.grad_sweeps
+    lat = kmc.Lattice(descs, seed)
+    stream = torch.cuda.current_stream()
+    lat.run(2, 1, kmc.F_PERSISTENT)
+    fwd = timed(lambda: lat.run(n, 10, kmc.F_PERSISTENT | kmc.F_CHECKPOINT), stream)
+    out = torch.empty((len(descs), n // 10, 2), dtype=torch.float64, device="cuda")
+    bwd = timed(lambda: lat.score(n // 10, out), stream)
+    ticks = n * sum(x["L"] ** 2 for x in descs)
+    lat.close()
+    return dict(fwd=fwd, bwd=bwd, ticks=ticks, overhead=(fwd + bwd) / fwd - 1.0,
+                replicas=len(descs), sweeps=n)
+
+
+def parity_prefix(kmc, workloads):
+    """Two sweeps of the benchmark workload checked against the oracle."""
+    import numpy as np
+
+    from oracle import kmco
+    seed, descs, _ = workloads.single_1024(2.269)
+    d = descs[0]
+    lat = kmc.Lattice(descs, seed)
+    lat.run(2, 1)
+    g, s = lat.records()[0], lat.spins(0)
+    lat.close()
+    o = kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
+                     steps_per_visit=d["steps_per_visit"], seed=seed, replica=0)
+    r = o.run(2, 1)
+    ok = all(np.array_equal(g[f], r[f]) for f in ("M", "B", "events", "steps"))
+    ok = ok and np.array_equal(s, o.spins()) and np.allclose(g["t"], r["t"], rtol=1e-12)
+    return bool(ok)
+
+
+def cpu_baseline(budget_s):
+    """The serial oracle, as it stands, on the benchmark workload: sweeps of
+    the 1024^2 lattice until about budget_s seconds of one core are used."""
+    from oracle import build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    from oracle import kmco
+    from paper_1403_4674_amd import workloads
+    seed, descs, _ = workloads.single_1024(2.269)
+    d = descs[0]
+    o = kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
+                     steps_per_visit=d["steps_per_visit"], seed=seed, replica=0)
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.run(1, 1)
+        n += 1
+    sec = time.perf_counter() - t0
+    return dict(value=n * d["L"] ** 2 / sec, unit="site-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{n} sweeps of the 1024x1024 lattice (32x32 domains, N_I=1024, "
+                       f"T=2.269) from the random start, serial C oracle, 1 thread, "
+                       f"{sec:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--graph", action="store_true", help="replay sweeps from a hipGraph")
+    ap.add_argument("--batched-sweeps", type=int, default=40)
+    ap.add_argument("--grad-sweeps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the method's replicas and domains are "
+              "run on a single MI355X here; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1403_4674_amd import kmc, workloads
+    torch.cuda.set_device(0)
+    # every context of this run is bound to one dedicated stream; the timing
+    # events are recorded on that same stream
+    torch.cuda.set_stream(torch.cuda.Stream())
+    kmc.use_torch_allocator()
+
+    p = plain(args, kmc, workloads)
+    value = p["ticks"] / p["sec"]
+    per_launch = p["sec"] / p["launches"]
+    d = p["desc"]
+    ops = OPS_PER_TICK * p["ticks"] + OPS_PER_EVENT * p["events"]
+    achieved = ops / p["sec"]
+    line = {
+        "metric": "site-updates/s (plain vs batched replicas) + backward overhead at "
+                  "bit-exact oracle match",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": p["sec"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain",
+                   "L": d["L"], "tile": d["tile"], "steps_per_visit": d["steps_per_visit"],
+                   "T": d["T"], "seed": p["seed"], "graph": bool(args.graph)},
+        "events_per_s": p["events"] / p["sec"],
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_phase<uint32_t,false>",
+            "achieved": achieved / 1e12,
+            "peak": ALU_PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s",
+            "frac": achieved / ALU_PEAK_LANE_OPS,
+            "traffic": None,
+            "per_launch_ms": per_launch * 1e3,
+            "ops_per_launch": ops / p["launches"],
+        },
+    }
+    if not args.no_extras:
+        b = batched(args, kmc, workloads)
+        g = backward(args, kmc, workloads)
+        line["batched"] = {"value": b["ticks"] / b["sec"], "unit": "site-updates/s",
+                           "replicas": b["replicas"], "sweeps": b["sweeps"],
+                           "vs_plain": (b["ticks"] / b["sec"]) / value}
+        line["backward"] = {"fwd_site_updates_per_s": g["ticks"] / g["fwd"],
+                            "overhead": g["overhead"], "replicas": g["replicas"],
+                            "sweeps": g["sweeps"],
+                            "fwd_plus_bwd_vs_plain": (g["ticks"] / (g["fwd"] + g["bwd"]))
+                            / value}
+        line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * kmc.h -- C-ABI of libkmc, the MI355X (gfx950) implementation of
+ * domain-decomposed sequential-update kinetic Monte Carlo
+ * (Nilmeier & Marian, "A rigorous sequential update strategy for parallel
+ * kinetic Monte Carlo simulation").
+ *
+ * The model (Appendix A): a periodic L x L Ising lattice with energy
+ *   H = -J sum_<ij> s_i s_j - h sum_i s_i        (Eq. (Hamiltonian Definition),
+ *                                                 extended by the field h),
+ * single-spin-flip rates w = Barker 1/(1+e^{dE/T}) as in Eq. (Glauber_TM),
+ * or Metropolis min(1, e^{-dE/T}).
+ *
+ * The method (Sec. 2.2): the lattice is cut into equal square domains of
+ * side B (fixed for the run, Fig. 1).  A domain process runs N_I ticks of the
+ * single-site kernel with the neighbouring spins (the halo) frozen.  Domains
+ * are coloured by a 4-colour checkerboard; domains of one colour do not
+ * interact and run concurrently.  Each sweep visits the colours in a
+ * schedule drawn uniformly from the 4! orders (Eq. (schedule), Eq. (sum of
+ * sequential tms)) or in the self-reverse palindrome ABCDDCBA, so detailed
+ * balance holds at sweep endpoints (Eq. (general reversibility condition)).
+ * Within a tick, event choice is n-fold way over 10 rate classes with Q32
+ * integer rates; each accepted event advances the domain clock by -ln(u)/R
+ * (Eq. (Poisson Distribution) and the residence time tau_S = 1/R).
+ *
+ * Conventions for every call:
+ *  - Every call returns a kmc_status; nothing is thrown or aborted across
+ *    the ABI.  On failure the context (when there is one) keeps a message
+ *    readable with kmc_last_error().
+ *  - A context is bound to one device and one HIP stream and is not
+ *    thread-safe.  Calls that launch work are asynchronous on that stream
+ *    unless stated otherwise.
+ *  - Inputs are copied; outputs are caller-owned memory.
+ *  - Lattices are row-major int8 with values +1 / -1.
+ */
+#ifndef KMC_H
+#define KMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kmc_ctx kmc_ctx;
+
+typedef enum {
+    KMC_OK = 0,
+    KMC_EINVAL = -1,        /* invalid argument or descriptor               */
+    KMC_ENOMEM = -2,        /* device or host allocation failed             */
+    KMC_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed   */
+    KMC_ESTATE = -4,        /* call not valid in the context's state        */
+    KMC_EUNSUPPORTED = -5   /* valid for the method, not for this library   */
+} kmc_status;
+
+enum { KMC_RATE_METROPOLIS = 0, KMC_RATE_BARKER = 1 };
+enum { KMC_SCHED_RANDOM_PERM = 0, KMC_SCHED_PALINDROME = 1 };
+enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
+
+/* flags of kmc_run_schedule */
+#define KMC_F_CHECKPOINT 0x1u  /* save the start state for kmc_backward_score */
+#define KMC_F_PERSISTENT 0x2u  /* one persistent launch: one wavefront owns a
+                                  replica and runs all of its sweeps          */
+#define KMC_F_GRAPH 0x4u       /* phase-by-phase path replayed from a captured
+                                  hipGraph                                     */
+/* flags of kmc_backward_score and kmc_observables */
+#define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
+                                  enqueued on the context stream, no sync     */
+
+/* One replica.  Domain side `tile` = B: L % B == 0, B % 4 == 0, 4 <= B <= 64
+ * and L/B even (a 4-colour checkerboard; the paper's Fig. 1 partition with
+ * N_D = (L/B)^2).  steps_per_visit = N_I ticks per domain process
+ * (Sec. 2.2); 0 selects B*B (one Monte Carlo step per site per visit). */
+typedef struct {
+    double J, h, T;            /* coupling, field, k_B T (> 0)              */
+    int32_t L;                 /* lattice side                              */
+    int32_t tile;              /* domain side B                             */
+    int32_t steps_per_visit;   /* N_I, >= 0                                 */
+    int32_t rate_model;        /* KMC_RATE_*                                */
+    int32_t schedule;          /* KMC_SCHED_*                               */
+    int32_t init;              /* KMC_INIT_*                                */
+} kmc_replica_desc;
+
+/* Observables at a sweep endpoint, the only points where statistics are
+ * valid (Sec. 2.3). */
+typedef struct {
+    int64_t sweep;   /* sweeps completed since kmc_init_lattice            */
+    int64_t M;       /* sum of spins                                        */
+    int64_t B;       /* sum over right and down bonds of s_i s_j            */
+    int64_t events;  /* accepted flips since kmc_init_lattice               */
+    int64_t steps;   /* ticks since kmc_init_lattice: N_I per domain visit,
+                        the integer time of Eq. (CK_parallel in s)          */
+    double t;        /* mean over domains of the per-domain event clocks    */
+} kmc_record;
+
+/* Routes the library's device allocations through a caller allocator (for
+ * instance a framework's caching allocator).  NULL restores hipMalloc /
+ * hipFree.  Applies to contexts created afterwards. */
+typedef void *(*kmc_alloc_fn)(size_t bytes, void *user);
+typedef void (*kmc_free_fn)(void *ptr, void *user);
+kmc_status kmc_set_device_allocator(kmc_alloc_fn alloc, kmc_free_fn free_fn,
+                                    void *user);
+
+/* Per-class rate table of one replica (Appendix A, Eq. (Glauber_TM)).
+ * Class c = 5*[s=+1] + k, k = number of up neighbours (0..4), flip energy
+ * dE = 2 s (J (2k-4) + h).  r[c] = min(2^32, floor(w 2^32 + 1/2)) is the Q32
+ * rate used for every decision; w, gJ = d ln w/dJ, gh = d ln w/dh are FP64.
+ * Host-only, no device needed.  Returns KMC_EINVAL for T <= 0, a non-finite
+ * parameter or an unknown model. */
+kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_model,
+                          uint64_t r[10], double w[10], double gJ[10],
+                          double gh[10]);
+
+/* Creates a context holding n_rep replicas on the current HIP device and
+ * initialises their lattices (Sec. 3: the paper's systems are periodic
+ * square lattices with a given start configuration).
+ *   d           host array of n_rep descriptors (copied)
+ *   seed        64-bit key of the counter-based generator; every random
+ *               number is Philox4x32-10(key = seed, counter = (tick,
+ *               domain | visit<<20 | stream<<24, sweep, replica))
+ *   given_spins host int8 array with sum over replicas of L*L values,
+ *               replicas concatenated in order; read only for replicas whose
+ *               init is KMC_INIT_GIVEN, may be NULL otherwise
+ *   hip_stream  hipStream_t for all work of this context; NULL = null stream
+ * Validation failures return KMC_EINVAL and create nothing; *out is set only
+ * on success.  Synchronises the stream before returning. */
+kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
+                            int32_t n_rep, uint64_t seed,
+                            const int8_t *given_spins, void *hip_stream);
+
+/* Runs n_sweeps schedule sweeps of every replica (Eq. (schedule): each sweep
+ * visits every domain once, twice for the palindrome, with a new schedule
+ * per sweep).  After the i-th sweep of this call (1-based) a record is
+ * appended for every replica when i % record_every == 0.  Asynchronous.
+ * Flags: KMC_F_CHECKPOINT keeps the start state so that kmc_backward_score
+ * can replay this call; KMC_F_PERSISTENT selects the one-launch batched
+ * kernel; KMC_F_GRAPH replays the phase-by-phase launches from a hipGraph.
+ * All paths produce bit-identical lattices, events and records.
+ * Errors: KMC_EINVAL (n_sweeps < 0, record_every < 1), KMC_ENOMEM, KMC_EDEVICE. */
+kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t record_every,
+                            uint32_t flags);
+
+/* Copies all records so far: out[rep * capacity + k] for replica rep and
+ * record k < min(capacity, *n_rec_out).  *n_rec_out receives the number of
+ * records per replica.  out may be NULL to query the count.  Host output
+ * synchronises the stream; with KMC_F_DEVICE_OUT out is device memory and
+ * the copy is only enqueued. */
+kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capacity,
+                           int64_t *n_rec_out, uint32_t flags);
+
+/* Likelihood-ratio path score of the last kmc_run_schedule call made with
+ * KMC_F_CHECKPOINT: replays that call from its saved start state with a
+ * dedicated kernel and accumulates, for every tick, d ln P/d(J, h) of the
+ * tick chain (an event of class c adds d ln w_c/d theta; a null tick adds
+ * d ln(1 - R_w/n_d)/d theta with R_w the domain's total FP64 rate).  Output
+ * score[(rep * capacity + k) * 2 + {0: J, 1: h}] for interval k: the ticks of
+ * sweeps (k*record_every, (k+1)*record_every] of that call; the number of
+ * intervals is ceil(n_sweeps / record_every) and must be <= capacity.
+ * The live state of the context is not changed.  KMC_ESTATE without a
+ * checkpoint.  Host output synchronises; KMC_F_DEVICE_OUT enqueues only. */
+kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capacity,
+                              uint32_t flags);
+
+/* Copies replica `replica`'s lattice (L*L int8, row-major) to host memory.
+ * Synchronises. */
+kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out);
+
+/* Copies the per-domain clock sums and their compensation terms (N_D
+ * doubles each, domain d = ty*(L/B) + tx) and per-domain event counts
+ * (N_D int64) of one replica to host memory; any pointer may be NULL.
+ * Synchronises. */
+kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *clk_sum,
+                                double *clk_comp, int64_t *events);
+
+/* Number of replicas, and the number of domains of one replica. */
+kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
+                        int32_t *n_domains);
+
+/* Message of the last failed call on c (never NULL). */
+const char *kmc_last_error(const kmc_ctx *c);
+
+/* Releases every device buffer of c after synchronising its stream. */
+void kmc_destroy(kmc_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,683 @@
+// kmc.hip -- host side of libkmc: the C-ABI declared in include/kmc.h.
+//
+// Owns the device buffers of a context, validates descriptors, builds the
+// per-replica Q32 rate tables on the host (the GPU never evaluates exp for a
+// decision), and enqueues the kernels of kmc_device.h on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kmc.h"
+#include "kmc_device.h"
+
+using kmcdev::Ctl;
+using kmcdev::Dom;
+using kmcdev::KParams;
+using kmcdev::Rates;
+using kmcdev::Record;
+using kmcdev::Rep;
+using kmcdev::RepAcc;
+
+static_assert(sizeof(kmc_record) == sizeof(Record), "record layout");
+
+// ------------------------------------------------------------ allocation
+
+static kmc_alloc_fn g_alloc = nullptr;
+static kmc_free_fn g_free = nullptr;
+static void *g_alloc_user = nullptr;
+
+extern "C" kmc_status kmc_set_device_allocator(kmc_alloc_fn alloc, kmc_free_fn free_fn,
+                                               void *user) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return KMC_EINVAL;
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_user = user;
+    return KMC_OK;
+}
+
+struct kmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;       // caller's stream, NULL = null stream
+    hipStream_t graph_stream = nullptr; // owned, for graph replay on the null stream
+    kmc_alloc_fn alloc = nullptr;
+    kmc_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
+
+    int32_t n_rep = 0;
+    uint64_t seed = 0;
+    std::vector<kmc_replica_desc> desc;
+    std::vector<Rep> reps;
+    std::vector<Rates> rates;
+    int64_t spin_bytes = 0;
+    int32_t n_dom = 0;
+    int32_t n_tasks = 0, n_tasks32 = 0;
+    int32_t n_order32 = 0, n_order64 = 0;
+    int n_phase = 4;
+
+    Rep *d_reps = nullptr;
+    Rates *d_rates = nullptr;
+    int8_t *d_spins = nullptr;
+    Dom *d_dom = nullptr;
+    RepAcc *d_acc = nullptr;
+    Record *d_rec = nullptr;
+    Ctl *d_ctl = nullptr;
+    int32_t *d_task_rep = nullptr;
+    int32_t *d_order = nullptr;
+    int64_t rec_cap = 0, n_rec = 0;
+    int64_t sweep = 0;
+
+    // checkpoint of the last run made with KMC_F_CHECKPOINT
+    bool have_ckpt = false;
+    int8_t *c_spins = nullptr;
+    Dom *c_dom = nullptr;
+    RepAcc *c_acc = nullptr;
+    int64_t ck_sweep = 0, ck_n_sweeps = 0;
+    int32_t ck_rec_every = 1;
+    uint32_t ck_flags = 0;
+
+    // replay buffers of kmc_backward_score
+    int8_t *r_spins = nullptr;
+    Dom *r_dom = nullptr;
+    RepAcc *r_acc = nullptr;
+    Ctl *r_ctl = nullptr;
+    double *d_bins = nullptr;
+    int64_t bins_cap = 0;
+    Record *d_tmp_rec = nullptr;
+    int64_t tmp_rec_cap = 0;
+
+    // captured phase-by-phase sweeps
+    hipGraphExec_t graph = nullptr;
+    int graph_sweeps = 0;
+
+    std::string err;
+};
+
+namespace {
+
+struct Fail {
+    kmc_status st;
+};
+
+void *dev_alloc(kmc_ctx *c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void *p = nullptr;
+    if (c->alloc) {
+        p = c->alloc(bytes, c->alloc_user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) {
+        c->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+        throw Fail{KMC_ENOMEM};
+    }
+    return p;
+}
+
+void dev_free(kmc_ctx *c, void *p) {
+    if (!p) return;
+    if (c->free_fn)
+        c->free_fn(p, c->alloc_user);
+    else
+        (void)hipFree(p);
+}
+
+template <typename T>
+T *alloc_n(kmc_ctx *c, int64_t n) {
+    return static_cast<T *>(dev_alloc(c, sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+}
+
+void hip_check(kmc_ctx *c, hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        throw Fail{KMC_EDEVICE};
+    }
+}
+
+void launch_check(kmc_ctx *c, const char *what) { hip_check(c, hipGetLastError(), what); }
+
+void fail(kmc_ctx *c, kmc_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    throw Fail{st};
+}
+
+// Per-class rates (Appendix A, Eq. (Glauber_TM)); classes c = 5*[s=+1] + k.
+kmc_status rate_table(double J, double h, double T, int32_t model, uint64_t r[10],
+                      double w[10], double gJ[10], double gh[10]) {
+    if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(J) || !std::isfinite(h))
+        return KMC_EINVAL;
+    if (model != KMC_RATE_METROPOLIS && model != KMC_RATE_BARKER) return KMC_EINVAL;
+    for (int c = 0; c < 10; ++c) {
+        const int up = c / 5, k = c % 5;
+        const double s = up ? 1.0 : -1.0;
+        const double n = (double)(2 * k - 4);
+        const double dE = 2.0 * s * (J * n + h);
+        double wc, dlw;  // w and d ln w / d dE
+        if (model == KMC_RATE_METROPOLIS) {
+            if (dE <= 0.0) {
+                wc = 1.0;
+                dlw = 0.0;
+            } else {
+                wc = std::exp(-dE / T);
+                dlw = -1.0 / T;
+            }
+        } else {
+            wc = 1.0 / (1.0 + std::exp(dE / T));
+            dlw = -(1.0 - wc) / T;
+        }
+        double q = std::floor(wc * 4294967296.0 + 0.5);
+        if (q > 4294967296.0) q = 4294967296.0;
+        r[c] = (uint64_t)q;
+        w[c] = wc;
+        gJ[c] = dlw * (2.0 * s * n);
+        gh[c] = dlw * (2.0 * s);
+    }
+    return KMC_OK;
+}
+
+void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
+    auto bad = [&](const char *why) {
+        fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": " + why);
+    };
+    if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
+        bad("J, h must be finite and T > 0");
+    if (d.tile < 4 || d.tile > 64 || d.tile % 4) bad("tile must be a multiple of 4 in [4, 64]");
+    if (d.L < 2 * d.tile || d.L % d.tile) bad("L must be a multiple of tile, L >= 2 tile");
+    if ((d.L / d.tile) % 2) bad("L/tile must be even (4-colour checkerboard)");
+    if ((int64_t)(d.L / d.tile) * (d.L / d.tile) > (1 << 20)) bad("more than 2^20 domains");
+    if (d.steps_per_visit < 0) bad("steps_per_visit must be >= 0");
+    if (d.rate_model != KMC_RATE_METROPOLIS && d.rate_model != KMC_RATE_BARKER)
+        bad("unknown rate model");
+    if (d.schedule != KMC_SCHED_RANDOM_PERM && d.schedule != KMC_SCHED_PALINDROME)
+        bad("unknown schedule");
+    if (d.init < KMC_INIT_RANDOM || d.init > KMC_INIT_GIVEN) bad("unknown init");
+}
+
+KParams params(kmc_ctx *c) {
+    KParams K;
+    K.reps = c->d_reps;
+    K.rates = c->d_rates;
+    K.spins = c->d_spins;
+    K.dom = c->d_dom;
+    K.acc = c->d_acc;
+    K.rec = c->d_rec;
+    K.ctl = c->d_ctl;
+    K.task_rep = c->d_task_rep;
+    K.order = c->d_order;
+    K.bins = nullptr;
+    K.n_rep = c->n_rep;
+    K.n_order = 0;
+    K.n_bins = 0;
+    K.seed = c->seed;
+    K.write_records = 1;
+    K.task_begin = 0;
+    return K;
+}
+
+template <bool SCORE>
+void launch_sweep(kmc_ctx *c, KParams K) {
+    for (int p = 0; p < c->n_phase; ++p) {
+        if (c->n_tasks32) {
+            K.task_begin = 0;
+            hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE>), dim3(c->n_tasks32),
+                               dim3(64), 0, c->stream, K, p);
+        }
+        if (c->n_tasks > c->n_tasks32) {
+            K.task_begin = c->n_tasks32;
+            hipLaunchKernelGGL((kmcdev::k_phase<uint64_t, SCORE>),
+                               dim3(c->n_tasks - c->n_tasks32), dim3(64), 0, c->stream, K,
+                               p);
+        }
+    }
+    hipLaunchKernelGGL(kmcdev::k_sweep_end, dim3(c->n_rep), dim3(64), 0, c->stream, K);
+    hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, (int64_t)1);
+    launch_check(c, "phase launch");
+}
+
+template <bool SCORE>
+void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps) {
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    const int waves = kmcdev::kWavesPerPersistentGroup;
+    for (int g = 0; g < 2; ++g) {
+        const int n = g == 0 ? c->n_order32 : c->n_order64;
+        if (!n) continue;
+        K.order = c->d_order + (g == 0 ? 0 : c->n_order32);
+        K.n_order = n;
+        const int groups = std::min((n + waves - 1) / waves, cus * 8);
+        hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
+        if (g == 0)
+            hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
+                               dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
+                               n_sweeps, 0);
+        else
+            hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
+                               dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
+                               n_sweeps, 1);
+    }
+    hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
+    launch_check(c, "persistent launch");
+}
+
+void ensure_records(kmc_ctx *c, int64_t need) {
+    if (need <= c->rec_cap) return;
+    const int64_t cap = std::max<int64_t>(need, c->rec_cap * 2);
+    Record *p = alloc_n<Record>(c, cap * c->n_rep);
+    if (c->n_rec)
+        hip_check(c, hipMemcpyAsync(p, c->d_rec, sizeof(Record) * c->n_rec * c->n_rep,
+                                    hipMemcpyDeviceToDevice, c->stream),
+                  "record copy");
+    hip_check(c, hipStreamSynchronize(c->stream), "record copy");
+    dev_free(c, c->d_rec);
+    c->d_rec = p;
+    c->rec_cap = cap;
+    if (c->graph) {  // the captured graph holds the old record pointer
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
+void run_graph(kmc_ctx *c, int64_t n_sweeps) {
+    const int G = 16;
+    // The null stream cannot be captured: replay on a private blocking stream,
+    // which the null stream orders implicitly.
+    if (!c->stream && !c->graph_stream) {
+        hip_check(c, hipStreamCreate(&c->graph_stream), "stream create");
+    }
+    hipStream_t gs = c->stream ? c->stream : c->graph_stream;
+    hipStream_t saved = c->stream;
+    if (!c->graph) {
+        hipGraph_t g;
+        c->stream = gs;
+        hip_check(c, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal),
+                  "begin capture");
+        for (int i = 0; i < G; ++i) launch_sweep<false>(c, params(c));
+        c->stream = saved;
+        hip_check(c, hipStreamEndCapture(gs, &g), "end capture");
+        hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(c, e, "graph instantiate");
+        c->graph_sweeps = G;
+    }
+    int64_t i = 0;
+    for (; i + c->graph_sweeps <= n_sweeps; i += c->graph_sweeps)
+        hip_check(c, hipGraphLaunch(c->graph, gs), "graph launch");
+    for (; i < n_sweeps; ++i) launch_sweep<false>(c, params(c));
+}
+
+int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * d.L; }
+
+void destroy_buffers(kmc_ctx *c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    void *bufs[] = {c->d_reps,  c->d_rates, c->d_spins, c->d_dom,   c->d_acc,
+                    c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
+                    c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
+                    c->r_ctl,   c->d_bins,  c->d_tmp_rec};
+    for (void *p : bufs) dev_free(c, p);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_model,
+                                     uint64_t r[10], double w[10], double gJ[10],
+                                     double gh[10]) {
+    if (!r || !w || !gJ || !gh) return KMC_EINVAL;
+    return rate_table(J, h, T, rate_model, r, w, gJ, gh);
+}
+
+extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
+                                       int32_t n_rep, uint64_t seed,
+                                       const int8_t *given_spins, void *hip_stream) {
+    if (!out || !d || n_rep < 1) return KMC_EINVAL;
+    kmc_ctx *c = new (std::nothrow) kmc_ctx;
+    if (!c) return KMC_ENOMEM;
+    try {  // descriptors are checked before any device call
+        for (int rho = 0; rho < n_rep; ++rho) validate(c, d[rho], rho);
+    } catch (const Fail &f) {
+        std::fprintf(stderr, "kmc_init_lattice: %s\n", c->err.c_str());
+        delete c;
+        return f.st;
+    }
+    try {
+        c->alloc = g_alloc;
+        c->free_fn = g_free;
+        c->alloc_user = g_alloc_user;
+        hip_check(c, hipGetDevice(&c->device), "hipGetDevice");
+        c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
+        c->n_rep = n_rep;
+        c->seed = seed;
+        c->desc.assign(d, d + n_rep);
+        c->reps.resize(n_rep);
+        c->rates.resize(n_rep);
+        int64_t off = 0;
+        int32_t dom = 0;
+        bool any_given = false;
+        for (int rho = 0; rho < n_rep; ++rho) {
+            const kmc_replica_desc &q = d[rho];
+            Rep &rp = c->reps[rho];
+            rp.L = q.L;
+            rp.B = q.tile;
+            rp.NT = q.L / q.tile;
+            rp.NI = q.steps_per_visit ? q.steps_per_visit : q.tile * q.tile;
+            rp.sched = q.schedule;
+            rp.ND = rp.NT * rp.NT;
+            rp.nd = (uint32_t)(q.tile * q.tile);
+            rp.thr = (uint32_t)(0u - rp.nd) % rp.nd;
+            rp.spin_off = off;
+            off += (bytes_of_spins(q) + 255) / 256 * 256;
+            rp.dom_off = dom;
+            dom += rp.ND;
+            rp.visits = q.schedule == KMC_SCHED_PALINDROME ? 2 : 1;
+            rp.init = q.init;
+            if (q.schedule == KMC_SCHED_PALINDROME) c->n_phase = 8;
+            if (q.init == KMC_INIT_GIVEN) any_given = true;
+            Rates &R = c->rates[rho];
+            double gJ[10], gh[10];
+            if (rate_table(q.J, q.h, q.T, q.rate_model, R.r, R.w, gJ, gh) != KMC_OK)
+                fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": rate table");
+            for (int k = 0; k < 10; ++k) {
+                R.gJ[k] = gJ[k];
+                R.gh[k] = gh[k];
+                R.aJ[k] = R.w[k] * gJ[k];
+                R.ah[k] = R.w[k] * gh[k];
+            }
+        }
+        if (any_given && !given_spins) fail(c, KMC_EINVAL, "KMC_INIT_GIVEN needs given_spins");
+        c->spin_bytes = off;
+        c->n_dom = dom;
+
+        // phase tasks: replicas with B <= 32 first (32-bit row masks)
+        std::vector<int32_t> task_rep;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int rho = 0; rho < n_rep; ++rho) {
+                Rep &rp = c->reps[rho];
+                if ((rp.B > 32) != (pass == 1)) continue;
+                rp.task_off = (int32_t)task_rep.size();
+                for (int i = 0; i < rp.ND / 4; ++i) task_rep.push_back(rho);
+                if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();
+            }
+        c->n_tasks = (int32_t)task_rep.size();
+        // persistent queues: costliest replica first within each group
+        std::vector<int32_t> order;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<int32_t> g;
+            for (int rho = 0; rho < n_rep; ++rho)
+                if ((c->reps[rho].B > 32) == (pass == 1)) g.push_back(rho);
+            std::stable_sort(g.begin(), g.end(), [&](int a, int b) {
+                const Rep &x = c->reps[a], &y = c->reps[b];
+                return (int64_t)x.NI * x.ND * x.visits > (int64_t)y.NI * y.ND * y.visits;
+            });
+            (pass == 0 ? c->n_order32 : c->n_order64) = (int32_t)g.size();
+            order.insert(order.end(), g.begin(), g.end());
+        }
+
+        c->d_reps = alloc_n<Rep>(c, n_rep);
+        c->d_rates = alloc_n<Rates>(c, n_rep);
+        c->d_spins = alloc_n<int8_t>(c, off);
+        c->d_dom = alloc_n<Dom>(c, dom);
+        c->d_acc = alloc_n<RepAcc>(c, n_rep);
+        c->d_ctl = alloc_n<Ctl>(c, 1);
+        c->d_task_rep = alloc_n<int32_t>(c, c->n_tasks);
+        c->d_order = alloc_n<int32_t>(c, n_rep);
+        hipStream_t s = c->stream;
+        hip_check(c, hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Rep) * n_rep,
+                                    hipMemcpyHostToDevice, s), "copy reps");
+        hip_check(c, hipMemcpyAsync(c->d_rates, c->rates.data(), sizeof(Rates) * n_rep,
+                                    hipMemcpyHostToDevice, s), "copy rates");
+        hip_check(c, hipMemcpyAsync(c->d_task_rep, task_rep.data(),
+                                    sizeof(int32_t) * std::max<size_t>(task_rep.size(), 1),
+                                    hipMemcpyHostToDevice, s), "copy tasks");
+        hip_check(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * n_rep,
+                                    hipMemcpyHostToDevice, s), "copy order");
+        hip_check(c, hipMemsetAsync(c->d_dom, 0, sizeof(Dom) * std::max(dom, 1), s), "zero");
+        hip_check(c, hipMemsetAsync(c->d_acc, 0, sizeof(RepAcc) * n_rep, s), "zero");
+        hip_check(c, hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s), "zero");
+        if (any_given) {
+            int64_t src = 0;
+            for (int rho = 0; rho < n_rep; ++rho) {
+                const int64_t nb = bytes_of_spins(d[rho]);
+                if (d[rho].init == KMC_INIT_GIVEN) {
+                    for (int64_t i = 0; i < nb; ++i)
+                        if (given_spins[src + i] != 1 && given_spins[src + i] != -1)
+                            fail(c, KMC_EINVAL, "given spins must be +1 or -1");
+                    hip_check(c, hipMemcpyAsync(c->d_spins + c->reps[rho].spin_off,
+                                                given_spins + src, nb,
+                                                hipMemcpyHostToDevice, s),
+                              "copy given spins");
+                }
+                src += nb;
+            }
+        }
+        int maxL = 0;
+        for (auto &q : c->desc) maxL = std::max(maxL, q.L);
+        KParams K = params(c);
+        const int64_t maxN = (int64_t)maxL * maxL;
+        hipLaunchKernelGGL(kmcdev::k_init_spins,
+                           dim3((unsigned)((maxN / 128 + 255) / 256 + 1), n_rep), dim3(256),
+                           0, s, K);
+        hipLaunchKernelGGL(kmcdev::k_init_obs, dim3((unsigned)((maxN + 255) / 256), n_rep),
+                           dim3(256), 0, s, K);
+        hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->d_ctl, (int64_t)0,
+                           (int64_t)0, (int64_t)1, (int64_t)0);
+        launch_check(c, "init launch");
+        hip_check(c, hipStreamSynchronize(s), "init sync");
+    } catch (const Fail &f) {
+        // the message is lost with the context; report it on stderr
+        std::fprintf(stderr, "kmc_init_lattice: %s\n", c->err.c_str());
+        destroy_buffers(c);
+        delete c;
+        return f.st;
+    }
+    *out = c;
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t record_every,
+                                       uint32_t flags) {
+    if (!c) return KMC_EINVAL;
+    try {
+        if (n_sweeps < 0 || record_every < 1)
+            fail(c, KMC_EINVAL, "n_sweeps must be >= 0 and record_every >= 1");
+        if (c->sweep + n_sweeps > 0xFFFFFFFFll)
+            fail(c, KMC_EINVAL, "sweep counter would exceed 2^32 - 1");
+        if ((flags & KMC_F_PERSISTENT) && (flags & KMC_F_GRAPH))
+            fail(c, KMC_EINVAL, "KMC_F_PERSISTENT and KMC_F_GRAPH are exclusive");
+        if (n_sweeps == 0) return KMC_OK;
+        ensure_records(c, c->n_rec + n_sweeps / record_every);
+        if (flags & KMC_F_CHECKPOINT) {
+            if (!c->c_spins) {
+                c->c_spins = alloc_n<int8_t>(c, c->spin_bytes);
+                c->c_dom = alloc_n<Dom>(c, c->n_dom);
+                c->c_acc = alloc_n<RepAcc>(c, c->n_rep);
+            }
+            hip_check(c, hipMemcpyAsync(c->c_spins, c->d_spins, c->spin_bytes,
+                                        hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+            hip_check(c, hipMemcpyAsync(c->c_dom, c->d_dom, sizeof(Dom) * c->n_dom,
+                                        hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+            hip_check(c, hipMemcpyAsync(c->c_acc, c->d_acc, sizeof(RepAcc) * c->n_rep,
+                                        hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+            c->have_ckpt = true;
+            c->ck_sweep = c->sweep;
+            c->ck_n_sweeps = n_sweeps;
+            c->ck_rec_every = record_every;
+            c->ck_flags = flags;
+        }
+        KParams K = params(c);
+        hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, c->stream, c->d_ctl,
+                           (int64_t)0, c->n_rec, (int64_t)record_every, c->sweep);
+        if (flags & KMC_F_PERSISTENT)
+            launch_persistent<false>(c, K, c->sweep, n_sweeps);
+        else if (flags & KMC_F_GRAPH)
+            run_graph(c, n_sweeps);
+        else
+            for (int64_t i = 0; i < n_sweeps; ++i) launch_sweep<false>(c, K);
+        c->n_rec += n_sweeps / record_every;
+        c->sweep += n_sweeps;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capacity,
+                                      int64_t *n_rec_out, uint32_t flags) {
+    if (!c) return KMC_EINVAL;
+    try {
+        if (n_rec_out) *n_rec_out = c->n_rec;
+        if (!out) return KMC_OK;
+        if (capacity < 0) fail(c, KMC_EINVAL, "capacity must be >= 0");
+        const int64_t n = std::min(capacity, c->n_rec);
+        if (n == 0) return KMC_OK;
+        if (flags & KMC_F_DEVICE_OUT) {
+            const int64_t tot = (int64_t)c->n_rep * c->n_rec;
+            hipLaunchKernelGGL(kmcdev::k_transpose_records, dim3((unsigned)((tot + 255) / 256)),
+                               dim3(256), 0, c->stream, c->d_rec,
+                               reinterpret_cast<Record *>(out), c->n_rep, c->n_rec, capacity);
+            launch_check(c, "record transpose");
+            return KMC_OK;
+        }
+        std::vector<Record> h((size_t)c->n_rec * c->n_rep);
+        hip_check(c, hipMemcpyAsync(h.data(), c->d_rec, sizeof(Record) * h.size(),
+                                    hipMemcpyDeviceToHost, c->stream), "record copy");
+        hip_check(c, hipStreamSynchronize(c->stream), "record sync");
+        for (int rho = 0; rho < c->n_rep; ++rho)
+            for (int64_t k = 0; k < n; ++k)
+                std::memcpy(&out[rho * capacity + k], &h[k * c->n_rep + rho], sizeof(Record));
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capacity,
+                                         uint32_t flags) {
+    if (!c) return KMC_EINVAL;
+    try {
+        if (!c->have_ckpt)
+            fail(c, KMC_ESTATE, "no run with KMC_F_CHECKPOINT to replay");
+        const int64_t n_bins = (c->ck_n_sweeps + c->ck_rec_every - 1) / c->ck_rec_every;
+        if (!score || capacity < n_bins)
+            fail(c, KMC_EINVAL, "score buffer smaller than the number of intervals");
+        if (!c->r_spins) {
+            c->r_spins = alloc_n<int8_t>(c, c->spin_bytes);
+            c->r_dom = alloc_n<Dom>(c, c->n_dom);
+            c->r_acc = alloc_n<RepAcc>(c, c->n_rep);
+            c->r_ctl = alloc_n<Ctl>(c, 1);
+        }
+        if (n_bins > c->bins_cap) {
+            dev_free(c, c->d_bins);
+            c->d_bins = nullptr;
+            c->d_bins = alloc_n<double>(c, n_bins * c->n_rep * 2);
+            c->bins_cap = n_bins;
+        }
+        hipStream_t s = c->stream;
+        hip_check(c, hipMemcpyAsync(c->r_spins, c->c_spins, c->spin_bytes,
+                                    hipMemcpyDeviceToDevice, s), "replay copy");
+        hip_check(c, hipMemcpyAsync(c->r_dom, c->c_dom, sizeof(Dom) * c->n_dom,
+                                    hipMemcpyDeviceToDevice, s), "replay copy");
+        hip_check(c, hipMemcpyAsync(c->r_acc, c->c_acc, sizeof(RepAcc) * c->n_rep,
+                                    hipMemcpyDeviceToDevice, s), "replay copy");
+        const int64_t nb = n_bins * c->n_rep * 2;
+        hipLaunchKernelGGL(kmcdev::k_fill_f64, dim3((unsigned)((nb + 255) / 256)), dim3(256),
+                           0, s, c->d_bins, nb, 0.0);
+        KParams K = params(c);
+        K.spins = c->r_spins;
+        K.dom = c->r_dom;
+        K.acc = c->r_acc;
+        K.ctl = c->r_ctl;
+        K.bins = c->d_bins;
+        K.n_bins = (int32_t)n_bins;
+        K.write_records = 0;
+        hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
+                           (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
+        if (c->ck_flags & KMC_F_PERSISTENT)
+            launch_persistent<true>(c, K, c->ck_sweep, c->ck_n_sweeps);
+        else
+            for (int64_t i = 0; i < c->ck_n_sweeps; ++i) launch_sweep<true>(c, K);
+        const hipMemcpyKind kind =
+            (flags & KMC_F_DEVICE_OUT) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        hip_check(c, hipMemcpy2DAsync(score, (size_t)capacity * 2 * sizeof(double), c->d_bins,
+                                      (size_t)n_bins * 2 * sizeof(double),
+                                      (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind, s),
+                  "score copy");
+        if (!(flags & KMC_F_DEVICE_OUT))
+            hip_check(c, hipStreamSynchronize(s), "score sync");
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out) {
+    if (!c || !out || replica < 0 || replica >= c->n_rep) {
+        if (c) c->err = "kmc_get_spins: bad replica or output";
+        return KMC_EINVAL;
+    }
+    try {
+        const Rep &rp = c->reps[replica];
+        hip_check(c, hipMemcpyAsync(out, c->d_spins + rp.spin_off, (size_t)rp.L * rp.L,
+                                    hipMemcpyDeviceToHost, c->stream), "spin copy");
+        hip_check(c, hipStreamSynchronize(c->stream), "spin sync");
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *clk_sum,
+                                           double *clk_comp, int64_t *events) {
+    if (!c || replica < 0 || replica >= c->n_rep) {
+        if (c) c->err = "kmc_get_domain_state: bad replica";
+        return KMC_EINVAL;
+    }
+    try {
+        const Rep &rp = c->reps[replica];
+        std::vector<Dom> h(rp.ND);
+        hip_check(c, hipMemcpyAsync(h.data(), c->d_dom + rp.dom_off, sizeof(Dom) * rp.ND,
+                                    hipMemcpyDeviceToHost, c->stream), "domain copy");
+        hip_check(c, hipStreamSynchronize(c->stream), "domain sync");
+        for (int i = 0; i < rp.ND; ++i) {
+            if (clk_sum) clk_sum[i] = h[i].clk_sum;
+            if (clk_comp) clk_comp[i] = h[i].clk_comp;
+            if (events) events[i] = h[i].events;
+        }
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+extern "C" kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
+                                   int32_t *n_domains) {
+    if (!c) return KMC_EINVAL;
+    if (n_rep) *n_rep = c->n_rep;
+    if (n_domains) {
+        if (replica < 0 || replica >= c->n_rep) return KMC_EINVAL;
+        *n_domains = c->reps[replica].ND;
+    }
+    return KMC_OK;
+}
+
+extern "C" const char *kmc_last_error(const kmc_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+extern "C" void kmc_destroy(kmc_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph_stream) (void)hipStreamSynchronize(c->graph_stream);
+    destroy_buffers(c);
+    if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
+    delete c;
+}

@@ -1,0 +1,792 @@
+// kmc_device.h -- gfx950 kernels of libkmc.
+//
+// One 64-lane wavefront runs one domain process (Sec. 2.2: N_I ticks of a
+// domain with its halo frozen).  Domains of one checkerboard colour never
+// touch, so they run as independent wavefronts; colours follow the sweep's
+// schedule (Eq. (schedule), Eq. (sum of sequential tms)).
+//
+// Wavefront layout of a B x B domain (4 <= B <= 64):
+//   * lane y < B holds row y of the domain as a bit mask (bit x = spin up),
+//     in a 32-bit word when B <= 32 and a 64-bit word otherwise;
+//   * the top and bottom halo rows are wave-uniform masks and the left and
+//     right halo columns one bit per lane; all are staged through LDS;
+//   * per-site class c = 5*[s=+1] + k (k = up neighbours) is never stored:
+//     three bit planes (k in binary) are rebuilt with two lane shuffles and
+//     ~15 bitwise ops after each flip;
+//   * lanes 0..9 hold the class counts n_c, the Q32 class weights
+//     W_c = n_c r_c and their inclusive prefix (a 16-lane scan); R = P_9;
+//   * ticks are drawn 64 at a time, one per lane, and one ballot finds the
+//     first tick whose x falls below R: every earlier tick is a null tick,
+//     exactly as if the ticks were tested one by one.
+// Event selection (n-fold way): class = first c with x < P_c (ballot over
+// lanes 0..9); member j = floor((x - P_{c-1}) / r_c) (exact integer, FP64
+// quotient corrected by integer multiplies); the j-th member in ascending
+// row-major order is found by a 64-lane prefix scan of per-row popcounts and
+// a ballot, then a binary search inside the row's mask.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kmcdev {
+
+// Philox4x32-10 constants (Salmon et al., SC'11).
+constexpr uint32_t kMulA = 0xD2511F53u;
+constexpr uint32_t kMulB = 0xCD9E8D57u;
+constexpr uint32_t kKeyIncA = 0x9E3779B9u;
+constexpr uint32_t kKeyIncB = 0xBB67AE85u;
+
+// counter word 1 = domain | visit << 20 | stream << 24
+constexpr uint32_t kStreamTick = 0;
+constexpr uint32_t kStreamInit = 1;
+constexpr uint32_t kStreamSched = 2;
+constexpr uint32_t kStreamRetry0 = 3;
+constexpr int kMaxRetry = 12;
+
+constexpr int kLdsPerWave = 64 * 64 + 2 * 64;  // tile + top/bottom halo rows
+constexpr int kWavesPerPersistentGroup = 4;
+
+struct Rates {
+    uint64_t r[10];                       // Q32 rates
+    double w[10], aJ[10], ah[10];         // w, w*dlnw/dJ, w*dlnw/dh
+    double gJ[10], gh[10];                // dlnw/dJ, dlnw/dh
+};
+
+struct Rep {
+    int32_t L, B, NT, NI;   // lattice side, domain side, L/B, ticks per visit
+    int32_t sched, ND;      // schedule kind, number of domains
+    uint32_t nd, thr;       // sites per domain, 2^32 mod nd
+    int64_t spin_off;       // byte offset of the lattice
+    int32_t dom_off;        // first domain record
+    int32_t task_off;       // first phase task
+    int32_t visits;         // visits of each domain per sweep (1 or 2)
+    int32_t init;           // kmc_init kind
+};
+
+struct Dom {
+    double clk_sum, clk_comp;  // compensated event clock
+    int64_t events;
+    int64_t pad;
+};
+
+struct RepAcc {
+    int64_t M, B, events, pad;  // running totals (M, B include the start state)
+};
+
+struct Record {
+    int64_t sweep, M, B, events, steps;
+    double t;
+};
+
+struct Ctl {
+    int64_t sweep;      // absolute index of the next sweep
+    int64_t run_done;   // sweeps done in the current run
+    int64_t rec_base;   // records written before the current run
+    int64_t rec_every;  // record interval of the current run
+    int64_t queue;      // persistent work queue head
+    int64_t pad[3];
+};
+
+struct KParams {
+    const Rep *reps;
+    const Rates *rates;
+    int8_t *spins;
+    Dom *dom;
+    RepAcc *acc;
+    Record *rec;
+    Ctl *ctl;
+    const int32_t *task_rep;  // phase task -> replica
+    const int32_t *order;     // persistent queue order (costliest first)
+    double *bins;             // score bins [n_rep][n_bins][2]
+    int32_t n_rep;
+    int32_t n_order;          // persistent queue length
+    int32_t n_bins;
+    uint64_t seed;
+    int32_t write_records;
+    int32_t task_begin;       // first phase task of this launch
+};
+
+// ------------------------------------------------------------------ Philox
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (i) {
+            k0 += kKeyIncA;
+            k1 += kKeyIncB;
+        }
+        const uint32_t lo0 = kMulA * c0, hi0 = __umulhi(kMulA, c0);
+        const uint32_t lo1 = kMulB * c2, hi1 = __umulhi(kMulB, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Uniform index in [0, 24) of the colour order of (replica, sweep).
+__device__ inline int schedule_index(uint64_t seed, uint32_t rho, uint32_t w) {
+    for (uint32_t call = 0;; ++call) {
+        const uint4 o = philox(call, kStreamSched << 24, w, rho, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+        const uint32_t v[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint64_t m = (uint64_t)v[i] * 24u;
+            if ((uint32_t)m >= 16u) return (int)(m >> 32);
+        }
+    }
+}
+
+// Element p of the permutation of {0,1,2,3} with lexicographic rank idx.
+__device__ inline int perm_element(int idx, int p) {
+    int avail = 0xF;  // bit set = colour still available
+    const int radix[3] = {6, 2, 1};
+    int out = 0;
+    for (int i = 0; i <= p && i < 4; ++i) {
+        int a = i < 3 ? idx / radix[i] : 0;
+        if (i < 3) idx %= radix[i];
+        int pick = -1;
+        for (int c = 0; c < 4; ++c) {
+            if (avail & (1 << c)) {
+                if (a == 0) {
+                    pick = c;
+                    break;
+                }
+                --a;
+            }
+        }
+        avail &= ~(1 << pick);
+        out = pick;
+    }
+    return out;
+}
+
+// Colour and visit index of phase p of sweep w (phase p < 4 for the random
+// order, p < 8 for the palindrome ABCDDCBA); -1 when the phase is empty.
+__device__ inline int phase_colour(const Rep &rp, uint64_t seed, uint32_t rho,
+                                   uint32_t w, int p, int *visit) {
+    if (rp.sched == 1) {
+        const int pal = p < 4 ? p : 7 - p;
+        *visit = p < 4 ? 0 : 1;
+        return pal;
+    }
+    *visit = 0;
+    if (p >= 4) return -1;
+    return perm_element(schedule_index(seed, rho, w), p);
+}
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t rdl32(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+__device__ __forceinline__ uint64_t rdl64(uint64_t v, int lane) {
+    const uint32_t lo = rdl32((uint32_t)v, lane);
+    const uint32_t hi = rdl32((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t scan16(uint64_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        const uint64_t t = __shfl_up(v, o);
+        if ((lane & 15) >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double sum16_f64(double v) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void neumaier_add(double &sum, double &comp, double x) {
+    const double t = sum + x;
+    if (fabs(sum) >= fabs(x))
+        comp += (sum - t) + x;
+    else
+        comp += (x - t) + sum;
+    sum = t;
+}
+
+template <typename MT>
+__device__ __forceinline__ int popc(MT m) {
+    if constexpr (sizeof(MT) == 8)
+        return __popcll(m);
+    else
+        return __popc(m);
+}
+
+// Position of the n-th (0-based) set bit of m; n < popc(m).
+template <typename MT>
+__device__ __forceinline__ int nth_set_bit(MT m, int n) {
+    int pos = 0;
+    if constexpr (sizeof(MT) == 8) {
+        const int pc = __popc((uint32_t)m);
+        if (n >= pc) {
+            n -= pc;
+            m >>= 32;
+            pos += 32;
+        }
+    }
+    uint32_t v = (uint32_t)m;
+#pragma unroll
+    for (int width = 16; width >= 1; width >>= 1) {
+        const int pc = __popc(v & ((1u << width) - 1u));
+        if (n >= pc) {
+            n -= pc;
+            v >>= width;
+            pos += width;
+        }
+    }
+    return pos;
+}
+
+// Four row bytes (+1 / -1) -> four bits (1 = up).
+__device__ __forceinline__ uint32_t bytes_to_bits(uint32_t v) {
+    const uint32_t b = (~v >> 7) & 0x01010101u;
+    return (b | (b >> 7) | (b >> 14) | (b >> 21)) & 0xFu;
+}
+
+__device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v |= (((nib >> i) & 1u) ? 0x01u : 0xFFu) << (8 * i);
+    return v;
+}
+
+// Bit planes of the up-neighbour count k (k = s0 + 2 s1 + 4 s2) of every site
+// of this lane's row.
+template <typename MT>
+struct Planes {
+    MT s0, s1, s2;
+};
+
+template <typename MT>
+__device__ __forceinline__ Planes<MT> neighbour_planes(MT S, MT top, MT bot,
+                                                      MT hl, MT hr, int B,
+                                                      MT VM, int lane) {
+    MT U = __shfl_up(S, 1);
+    if (lane == 0) U = top;
+    MT D = __shfl_down(S, 1);
+    if (lane == B - 1) D = bot;
+    const MT Lf = ((S << 1) | hl) & VM;
+    const MT Rt = ((S >> 1) | (hr << (B - 1))) & VM;
+    U &= VM;
+    D &= VM;
+    const MT p1 = U ^ D, q1 = U & D;
+    const MT p2 = Lf ^ Rt, q2 = Lf & Rt;
+    const MT c0 = p1 & p2;
+    Planes<MT> P;
+    P.s0 = p1 ^ p2;
+    P.s1 = q1 ^ q2 ^ c0;
+    P.s2 = (q1 & q2) | (c0 & (q1 ^ q2));
+    return P;
+}
+
+template <typename MT>
+__device__ __forceinline__ MT class_mask(int c, MT S, const Planes<MT> &P, MT VM) {
+    const bool up = c >= 5;
+    const int k = up ? c - 5 : c;
+    MT m = up ? S : ~S;
+    m &= (k & 1) ? P.s0 : ~P.s0;
+    m &= (k & 2) ? P.s1 : ~P.s1;
+    m &= (k & 4) ? P.s2 : ~P.s2;
+    return m & VM;
+}
+
+template <typename MT>
+__device__ __forceinline__ int class_at(MT S, const Planes<MT> &P, int b) {
+    return 5 * (int)((S >> b) & 1) + (int)((P.s0 >> b) & 1) +
+           2 * (int)((P.s1 >> b) & 1) + 4 * (int)((P.s2 >> b) & 1);
+}
+
+struct VisitOut {
+    int64_t events;
+    int64_t dM, dB;
+    double sJ, sh;
+};
+
+// One domain process: N_I ticks of domain d (origin oy, ox) of the lattice
+// `lat` (side L, domain side B).  Executed by one full wavefront; `lds`
+// points at this wavefront's kLdsPerWave bytes.  The domain's compensated
+// clock in *dom is advanced; the changes of M, B and the event count are
+// returned (and the score when SCORE).
+template <typename MT, bool SCORE>
+__device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
+                                 const Rates *__restrict__ rt, int oy, int ox,
+                                 uint32_t d, uint32_t vis, uint32_t w,
+                                 uint32_t rho, uint64_t seed, Dom *dom,
+                                 uint8_t *lds) {
+    const int lane = __lane_id();
+    const int L = rp.L, B = rp.B, NI = rp.NI;
+    const int B4 = B >> 2;
+    const uint32_t nd = rp.nd, thr = rp.thr;
+
+    // ---- stage the tile and the top/bottom halo rows through LDS
+    uint8_t *tile = lds;
+    uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
+    for (int q = lane; q < B * B4; q += 64) {
+        const int row = q / B4, c4 = q - row * B4;
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(
+            lat + (int64_t)(oy + row) * L + ox + 4 * c4);
+        *reinterpret_cast<uint32_t *>(tile + row * B + 4 * c4) = v;
+    }
+    if (lane < 2 * B4) {
+        const int which = lane / B4, c4 = lane - which * B4;
+        const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
+        const uint32_t v =
+            *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + ox + 4 * c4);
+        *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) = v;
+    }
+    MT hl = 0, hr = 0;
+    if (lane < B) {
+        const int64_t rowbase = (int64_t)(oy + lane) * L;
+        hl = lat[rowbase + (ox - 1 + L) % L] > 0 ? 1 : 0;
+        hr = lat[rowbase + (ox + B) % L] > 0 ? 1 : 0;
+    }
+    wave_sync_lds();
+
+    const MT VM = lane < B ? (B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1))
+                           : (MT)0;
+    MT S = 0, top = 0, bot = 0;
+    for (int q = 0; q < B4; ++q) {
+        if (lane < B)
+            S |= (MT)bytes_to_bits(
+                     *reinterpret_cast<const uint32_t *>(tile + lane * B + 4 * q))
+                 << (4 * q);
+        top |= (MT)bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 4 * q))
+               << (4 * q);
+        bot |= (MT)bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 64 + 4 * q))
+               << (4 * q);
+    }
+    Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
+
+    // ---- class counts: per-row popcounts, reduced two classes per word
+    uint32_t n_lane = 0;  // lanes 0..9: n_c
+#pragma unroll
+    for (int c = 0; c < 10; c += 2) {
+        const uint32_t a = popc(class_mask<MT>(c, S, P, VM));
+        const uint32_t b = popc(class_mask<MT>(c + 1, S, P, VM));
+        const uint32_t s = wave_sum_u32(a | (b << 16));
+        if (lane == c) n_lane = s & 0xFFFFu;
+        if (lane == c + 1) n_lane = s >> 16;
+    }
+    const uint64_t r_lane = lane < 10 ? rt->r[lane] : 0;
+    uint64_t W = (uint64_t)n_lane * r_lane;
+    uint64_t Pinc = scan16(W, lane);
+    uint64_t R = rdl64(Pinc, 9);
+
+    double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0;
+    if constexpr (SCORE) {
+        if (lane < 10) {
+            w_lane = rt->w[lane];
+            aJ_lane = rt->aJ[lane];
+            ah_lane = rt->ah[lane];
+        }
+    }
+
+    VisitOut out{0, 0, 0, 0.0, 0.0};
+    double clk_sum = dom->clk_sum, clk_comp = dom->clk_comp;
+    uint32_t m_null = 0;  // null ticks since the last event (score)
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
+
+    auto null_score = [&](uint32_t m) {
+        // d ln(1 - R_w/n_d)/d theta per null tick, times m
+        const double nl = (double)n_lane;
+        const double Rw = sum16_f64(nl * w_lane);
+        const double RJ = sum16_f64(nl * aJ_lane);
+        const double Rh = sum16_f64(nl * ah_lane);
+        const double den = (double)nd - Rw;
+        if (den > 0.0) {
+            out.sJ += (double)m * (-RJ / den);
+            out.sh += (double)m * (-Rh / den);
+        }
+    };
+
+    for (int base = 0; base < NI; base += 64) {
+        const uint32_t t = (uint32_t)(base + lane);
+        const bool valid = base + lane < NI;
+        const uint4 o = philox(t, c1, w, rho, key0, key1);
+        uint64_t mm = (uint64_t)o.y * nd;
+        bool rej = valid && (uint32_t)mm < thr;
+        if (__ballot(rej)) {  // rare: redraw the slot on the retry streams
+            for (int k = 1; rej && k <= kMaxRetry; ++k) {
+                const uint4 o2 =
+                    philox(t, d | (vis << 20) | ((kStreamRetry0 + k - 1) << 24), w,
+                           rho, key0, key1);
+                mm = (uint64_t)o2.y * nd;
+                rej = (uint32_t)mm < thr;
+            }
+        }
+        const uint64_t x = ((mm >> 32) << 32) | o.x;
+        const uint64_t vmask = __ballot(valid);
+        uint64_t Rb = 0;  // this lane's R before its event (0: no event)
+        int pos = 0;
+        for (;;) {
+            const uint64_t lanes_left = pos >= 64 ? 0 : (vmask >> pos) << pos;
+            const uint64_t cand = __ballot(x < R) & lanes_left;
+            if (!cand) {
+                m_null += (uint32_t)__popcll(lanes_left);
+                break;
+            }
+            const int e = __ffsll((long long)cand) - 1;
+            m_null += (uint32_t)(e - pos);
+            const uint64_t xe = rdl64(x, e);
+            if (lane == e) Rb = R;
+
+            // rate class: first c with xe < P_c
+            const int c = __ffsll((long long)__ballot(lane < 10 && xe < Pinc)) - 1;
+            const uint64_t Pc = rdl64(Pinc - W, c);
+            const uint64_t rc = rdl64(r_lane, c);
+            const uint64_t a = xe - Pc;
+            uint64_t j = (uint64_t)floor((double)a / (double)rc);
+            if (j * rc > a)
+                --j;
+            else if ((j + 1) * rc <= a)
+                ++j;
+
+            if constexpr (SCORE) {
+                if (m_null) null_score(m_null);
+                out.sJ += rt->gJ[c];
+                out.sh += rt->gh[c];
+            }
+            m_null = 0;
+
+            // member j of class c in ascending row-major order
+            const MT cm = class_mask<MT>(c, S, P, VM);
+            const uint32_t cnt = (uint32_t)popc(cm);
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            const int ys = __ffsll((long long)__ballot(incl > (uint32_t)j)) - 1;
+            const int jl = (int)((uint32_t)j - (incl - cnt));
+            const int bitpos = nth_set_bit<MT>(cm, jl < 0 ? 0 : jl);
+            const int xs = (int)rdl32((uint32_t)bitpos, ys);
+
+            // class changes of the flipped site and its in-tile neighbours
+            const bool up = c >= 5;
+            const int k = up ? c - 5 : c;
+            const int delta = up ? -1 : 1;
+            const int cls_mid = class_at<MT>(S, P, xs);
+            const int cls_l = xs > 0 ? class_at<MT>(S, P, xs - 1) : 0;
+            const int cls_r = xs < B - 1 ? class_at<MT>(S, P, xs + 1) : 0;
+            const int cu = ys > 0 ? (int)rdl32((uint32_t)cls_mid, ys - 1) : -100;
+            const int cd = ys < B - 1 ? (int)rdl32((uint32_t)cls_mid, ys + 1) : -100;
+            const int cl = xs > 0 ? (int)rdl32((uint32_t)cls_l, ys) : -100;
+            const int cr = xs < B - 1 ? (int)rdl32((uint32_t)cls_r, ys) : -100;
+            int dn = (lane == (up ? c - 5 : c + 5)) - (lane == c);
+            dn += (lane == cu + delta) - (lane == cu);
+            dn += (lane == cd + delta) - (lane == cd);
+            dn += (lane == cl + delta) - (lane == cl);
+            dn += (lane == cr + delta) - (lane == cr);
+            n_lane = (uint32_t)((int)n_lane + dn);
+            W = (uint64_t)n_lane * r_lane;
+            Pinc = scan16(W, lane);
+            R = rdl64(Pinc, 9);
+
+            if (lane == ys) S ^= (MT)1 << xs;
+            P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
+
+            out.dM += up ? -2 : 2;
+            out.dB += (up ? -2 : 2) * (2 * k - 4);
+            ++out.events;
+            pos = e + 1;
+        }
+        // residence times -ln(u)/R_w of this batch's events
+        if (__ballot(Rb != 0)) {
+            double dt = 0.0;
+            if (Rb) {
+                const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
+                const double u = (double)(u53 + 1) * 0x1p-53;
+                dt = -log(u) * 4294967296.0 / (double)Rb;
+            }
+            neumaier_add(clk_sum, clk_comp, wave_sum_f64(dt));
+        }
+    }
+    if constexpr (SCORE) {
+        if (m_null) null_score(m_null);
+    }
+
+    // ---- write the tile back through LDS
+    if (lane < B) {
+        for (int q = 0; q < B4; ++q)
+            *reinterpret_cast<uint32_t *>(tile + lane * B + 4 * q) =
+                bits_to_bytes((uint32_t)(S >> (4 * q)) & 0xFu);
+    }
+    wave_sync_lds();
+    for (int q = lane; q < B * B4; q += 64) {
+        const int row = q / B4, c4 = q - row * B4;
+        *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
+            *reinterpret_cast<const uint32_t *>(tile + row * B + 4 * c4);
+    }
+    if (lane == 0) {
+        dom->clk_sum = clk_sum;
+        dom->clk_comp = clk_comp;
+        dom->events += out.events;
+    }
+    wave_sync_lds();  // LDS reads of the write-back finish before reuse
+    return out;
+}
+
+// Origin of the i-th domain of colour `col` (ascending domain index).
+__device__ __forceinline__ void colour_domain(const Rep &rp, int col, int i,
+                                              int *d, int *oy, int *ox) {
+    const int half = rp.NT >> 1;
+    const int tx = 2 * (i % half) + (col & 1);
+    const int ty = 2 * (i / half) + (col >> 1);
+    *d = ty * rp.NT + tx;
+    *oy = ty * rp.B;
+    *ox = tx * rp.B;
+}
+
+// Mean of the replica's domain clocks (wave-parallel, fixed order).
+__device__ inline double replica_time(const KParams &K, const Rep &rp, int lane) {
+    double s = 0.0, cpen = 0.0;
+    for (int dd = lane; dd < rp.ND; dd += 64) {
+        const Dom &dm = K.dom[rp.dom_off + dd];
+        neumaier_add(s, cpen, dm.clk_sum + dm.clk_comp);
+    }
+    return wave_sum_f64(s + cpen) / (double)rp.ND;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// Phase p of the current sweep: one wavefront per (replica, domain of the
+// phase's colour).  Launched once per phase; domains of a colour commute.
+template <typename MT, bool SCORE>
+__global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
+    const int task = K.task_begin + (int)blockIdx.x;
+    const int rho = K.task_rep[task];
+    const Rep rp = K.reps[rho];
+    const uint32_t w = (uint32_t)K.ctl->sweep;
+    int vis;
+    const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
+    if (col < 0) return;
+    int d, oy, ox;
+    colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
+    const VisitOut o = visit_domain<MT, SCORE>(
+        K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
+        (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+    if (__lane_id() == 0) {
+        if (o.events) {
+            atomicAdd((unsigned long long *)&K.acc[rho].M, (unsigned long long)o.dM);
+            atomicAdd((unsigned long long *)&K.acc[rho].B, (unsigned long long)o.dB);
+            atomicAdd((unsigned long long *)&K.acc[rho].events,
+                      (unsigned long long)o.events);
+        }
+        if constexpr (SCORE) {
+            const int64_t bin = K.ctl->run_done / K.ctl->rec_every;
+            double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
+            atomicAdd(b, o.sJ);
+            atomicAdd(b + 1, o.sh);
+        }
+    }
+}
+
+// End of a sweep: one wavefront per replica writes the record when due.
+__global__ __launch_bounds__(64) void k_sweep_end(KParams K) {
+    const int rho = blockIdx.x;
+    const Ctl c = *K.ctl;
+    const int64_t done = c.run_done + 1;
+    if (!K.write_records || done % c.rec_every) return;
+    const Rep rp = K.reps[rho];
+    const int lane = __lane_id();
+    const double t = replica_time(K, rp, lane);
+    if (lane == 0) {
+        const int64_t k = c.rec_base + done / c.rec_every - 1;
+        Record r;
+        r.sweep = c.sweep + 1;
+        r.M = K.acc[rho].M;
+        r.B = K.acc[rho].B;
+        r.events = K.acc[rho].events;
+        r.steps = (c.sweep + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
+        r.t = t;
+        K.rec[k * K.n_rep + rho] = r;
+    }
+}
+
+__global__ void k_advance(Ctl *ctl, int64_t n) {
+    ctl->sweep += n;
+    ctl->run_done += n;
+}
+
+__global__ void k_reset_queue(Ctl *ctl) { ctl->queue = 0; }
+
+__global__ void k_set_ctl(Ctl *ctl, int64_t run_done, int64_t rec_base,
+                          int64_t rec_every, int64_t sweep) {
+    ctl->run_done = run_done;
+    ctl->rec_base = rec_base;
+    ctl->rec_every = rec_every;
+    ctl->queue = 0;
+    ctl->sweep = sweep;
+}
+
+// Persistent batched form: each wavefront takes replicas from a queue
+// (costliest first) and runs all n_sweeps sweeps of each, every colour
+// phase and every domain in order; nothing is shared between wavefronts.
+template <typename MT, bool SCORE>
+__global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
+    KParams K, int64_t sweep0, int64_t run_done0, int64_t n_sweeps, int mt64) {
+    __shared__ __attribute__((aligned(16)))
+    uint8_t lds_all[kWavesPerPersistentGroup][kLdsPerWave];
+    uint8_t *lds = lds_all[threadIdx.x >> 6];
+    const int lane = __lane_id();
+    const int64_t rec_every = K.ctl->rec_every;
+    const int64_t rec_base = K.ctl->rec_base;
+    for (;;) {
+        int idx = 0;
+        if (lane == 0)
+            idx = (int)atomicAdd((unsigned long long *)&K.ctl->queue, 1ull);
+        idx = (int)rdl32((uint32_t)idx, 0);
+        if (idx >= K.n_order) return;
+        const int rho = K.order[idx];
+        const Rep rp = K.reps[rho];
+        if ((rp.B > 32) != (mt64 != 0)) continue;  // other template instance
+        RepAcc acc = K.acc[rho];
+        double sJ = 0.0, sh = 0.0;
+        for (int64_t i = 0; i < n_sweeps; ++i) {
+            const uint32_t w = (uint32_t)(sweep0 + i);
+            const int nphase = rp.sched == 1 ? 8 : 4;
+            for (int p = 0; p < nphase; ++p) {
+                int vis;
+                const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
+                const int per_colour = rp.ND >> 2;
+                for (int i2 = 0; i2 < per_colour; ++i2) {
+                    int d, oy, ox;
+                    colour_domain(rp, col, i2, &d, &oy, &ox);
+                    const VisitOut o = visit_domain<MT, SCORE>(
+                        K.spins + rp.spin_off, rp, K.rates + rho, oy, ox,
+                        (uint32_t)d, (uint32_t)vis, w, (uint32_t)rho, K.seed,
+                        K.dom + rp.dom_off + d, lds);
+                    acc.M += o.dM;
+                    acc.B += o.dB;
+                    acc.events += o.events;
+                    sJ += o.sJ;
+                    sh += o.sh;
+                }
+            }
+            const int64_t done = run_done0 + i + 1;
+            if (done % rec_every == 0 || i + 1 == n_sweeps) {
+                __threadfence();
+                if constexpr (SCORE) {
+                    if (lane == 0) {
+                        const int64_t bin = (done - 1) / rec_every;
+                        double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
+                        b[0] += sJ;
+                        b[1] += sh;
+                    }
+                    sJ = 0.0;
+                    sh = 0.0;
+                }
+                if (K.write_records && done % rec_every == 0) {
+                    const double t = replica_time(K, rp, lane);
+                    if (lane == 0) {
+                        const int64_t k = rec_base + done / rec_every - 1;
+                        Record r;
+                        r.sweep = (int64_t)w + 1;
+                        r.M = acc.M;
+                        r.B = acc.B;
+                        r.events = acc.events;
+                        r.steps = ((int64_t)w + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
+                        r.t = t;
+                        K.rec[k * K.n_rep + rho] = r;
+                    }
+                }
+            }
+        }
+        if (lane == 0) K.acc[rho] = acc;
+    }
+}
+
+// ------------------------------------------------------------ init kernels
+
+__global__ void k_init_spins(KParams K) {
+    const int rho = blockIdx.y;
+    const Rep rp = K.reps[rho];
+    const int64_t N = (int64_t)rp.L * rp.L;
+    const int64_t call = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (call * 128 >= N || rp.init == 2) return;
+    int8_t *lat = K.spins + rp.spin_off;
+    if (rp.init == 1) {
+        for (int i = 0; i < 128 && call * 128 + i < N; ++i) lat[call * 128 + i] = 1;
+        return;
+    }
+    const uint4 o = philox((uint32_t)call, kStreamInit << 24, 0u, (uint32_t)rho,
+                           (uint32_t)K.seed, (uint32_t)(K.seed >> 32));
+    const uint32_t v[4] = {o.x, o.y, o.z, o.w};
+    for (int i = 0; i < 128 && call * 128 + i < N; ++i)
+        lat[call * 128 + i] = ((v[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+}
+
+// M and B of the start lattice; one thread per site, int64 atomics.
+__global__ __launch_bounds__(256) void k_init_obs(KParams K) {
+    const int rho = blockIdx.y;
+    const Rep rp = K.reps[rho];
+    const int L = rp.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int m = 0, b = 0;
+    if (i < N) {
+        const int8_t *lat = K.spins + rp.spin_off;
+        const int y = (int)(i / L), x = (int)(i % L);
+        const int s = lat[i];
+        m = s;
+        b = s * (lat[(int64_t)y * L + (x + 1) % L] + lat[(int64_t)((y + 1) % L) * L + x]);
+    }
+    const uint32_t sm = wave_sum_u32((uint32_t)m);
+    const uint32_t sb = wave_sum_u32((uint32_t)b);
+    if (__lane_id() == 0 && (sm || sb)) {
+        atomicAdd((unsigned long long *)&K.acc[rho].M, (unsigned long long)(int64_t)(int32_t)sm);
+        atomicAdd((unsigned long long *)&K.acc[rho].B, (unsigned long long)(int64_t)(int32_t)sb);
+    }
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_transpose_records(const Record *in, Record *out, int n_rep,
+                                    int64_t n_rec, int64_t capacity) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_rep * n_rec) return;
+    const int64_t k = i / n_rep, rho = i % n_rep;
+    if (k < capacity) out[rho * capacity + k] = in[i];
+}
+
+}  // namespace kmcdev

@@ -1,0 +1,246 @@
+"""Python binding of libkmc (argument marshalling only).
+
+Every function here has the name of the C call it wraps (include/kmc.h) and
+does nothing but convert arguments; every step of the method runs in the
+HIP kernels of libkmc.so.  PyTorch provides the device memory (libkmc's
+allocations go through torch's caching allocator) and the HIP stream.
+There is no fallback: when libkmc.so is missing or no GPU is present the
+calls raise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkmc.so")
+
+KMC_OK, KMC_EINVAL, KMC_ENOMEM, KMC_EDEVICE, KMC_ESTATE, KMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RATE_METROPOLIS, RATE_BARKER = 0, 1
+SCHED_RANDOM_PERM, SCHED_PALINDROME = 0, 1
+INIT_RANDOM, INIT_ALL_UP, INIT_GIVEN = 0, 1, 2
+F_CHECKPOINT, F_PERSISTENT, F_GRAPH, F_DEVICE_OUT = 0x1, 0x2, 0x4, 0x10
+
+STATUS_NAMES = {0: "KMC_OK", -1: "KMC_EINVAL", -2: "KMC_ENOMEM", -3: "KMC_EDEVICE",
+                -4: "KMC_ESTATE", -5: "KMC_EUNSUPPORTED"}
+
+
+class KmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ReplicaDesc(C.Structure):
+    _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
+                ("L", C.c_int32), ("tile", C.c_int32), ("steps_per_visit", C.c_int32),
+                ("rate_model", C.c_int32), ("schedule", C.c_int32), ("init", C.c_int32)]
+
+
+RECORD_DTYPE = np.dtype([("sweep", "<i8"), ("M", "<i8"), ("B", "<i8"),
+                         ("events", "<i8"), ("steps", "<i8"), ("t", "<f8")])
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+_torch_hooks = None
+
+
+def lib():
+    """Loads libkmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "or python -m paper_1403_4674_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sigs = {
+            "kmc_set_device_allocator": ([_ALLOC_FN, _FREE_FN, P], I32),
+            "kmc_rate_table": ([C.c_double, C.c_double, C.c_double, I32, P, P, P, P], I32),
+            "kmc_init_lattice": ([C.POINTER(P), C.POINTER(ReplicaDesc), I32, C.c_uint64, P,
+                                  P], I32),
+            "kmc_run_schedule": ([P, I64, I32, C.c_uint32], I32),
+            "kmc_observables": ([P, P, I64, C.POINTER(I64), C.c_uint32], I32),
+            "kmc_backward_score": ([P, P, I64, C.c_uint32], I32),
+            "kmc_get_spins": ([P, I32, P], I32),
+            "kmc_get_domain_state": ([P, I32, P, P, P], I32),
+            "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
+            "kmc_last_error": ([P], C.c_char_p),
+            "kmc_destroy": ([P], None),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names the C-ABI exports (checked against include/kmc.h by the tests)."""
+    L = lib()
+    names = ["kmc_set_device_allocator", "kmc_rate_table", "kmc_init_lattice",
+             "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
+             "kmc_get_domain_state", "kmc_get_info", "kmc_last_error", "kmc_destroy"]
+    return [n for n in names if hasattr(L, n)]
+
+
+def _check(status, ctx=None):
+    if status != KMC_OK:
+        msg = lib().kmc_last_error(ctx).decode() if ctx else ""
+        raise KmcError(status, msg)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def use_torch_allocator():
+    """Routes libkmc's device allocations through torch's caching allocator."""
+    global _torch_hooks
+    import torch
+    if _torch_hooks is None:
+        def alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(nbytes)
+            except Exception:
+                return None
+
+        def free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        _torch_hooks = (_ALLOC_FN(alloc), _FREE_FN(free))
+    _check(lib().kmc_set_device_allocator(_torch_hooks[0], _torch_hooks[1], None))
+
+
+def kmc_rate_table(J, h, T, rate_model=RATE_METROPOLIS):
+    r = np.zeros(10, np.uint64)
+    w, gJ, gh = (np.zeros(10) for _ in range(3))
+    _check(lib().kmc_rate_table(J, h, T, rate_model, _ptr(r), _ptr(w), _ptr(gJ), _ptr(gh)))
+    return r, w, gJ, gh
+
+
+def make_descs(descs):
+    arr = (ReplicaDesc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = ReplicaDesc(float(d.get("J", 1.0)), float(d.get("h", 0.0)),
+                             float(d["T"]), int(d["L"]), int(d["tile"]),
+                             int(d.get("steps_per_visit", 0)),
+                             int(d.get("rate_model", RATE_METROPOLIS)),
+                             int(d.get("schedule", SCHED_RANDOM_PERM)),
+                             int(d.get("init", INIT_RANDOM)))
+    return arr
+
+
+def kmc_init_lattice(descs, seed, given_spins=None, stream=None):
+    """descs: list of dicts with keys L, tile, T and optional J, h,
+    steps_per_visit, rate_model, schedule, init.  stream: a hipStream_t
+    handle (int) or None for torch's current stream.  Returns the context."""
+    arr = make_descs(descs)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    g = None
+    if given_spins is not None:
+        g = np.ascontiguousarray(np.concatenate([np.asarray(x, np.int8).reshape(-1)
+                                                 for x in given_spins]))
+    ctx = C.c_void_p()
+    st = lib().kmc_init_lattice(C.byref(ctx), arr, len(descs), C.c_uint64(seed),
+                                _ptr(g) if g is not None else None,
+                                C.c_void_p(stream) if stream else None)
+    _check(st)
+    return ctx
+
+
+def kmc_run_schedule(ctx, n_sweeps, record_every=1, flags=0):
+    _check(lib().kmc_run_schedule(ctx, n_sweeps, record_every, flags), ctx)
+
+
+def kmc_observables(ctx, n_rep):
+    """All records so far as a [n_rep, n_rec] structured array (synchronises)."""
+    n = C.c_int64(0)
+    _check(lib().kmc_observables(ctx, None, 0, C.byref(n), 0), ctx)
+    out = np.zeros((n_rep, max(n.value, 1)), RECORD_DTYPE)
+    if n.value:
+        _check(lib().kmc_observables(ctx, _ptr(out), n.value, C.byref(n), 0), ctx)
+    return out[:, :n.value]
+
+
+def kmc_observables_device(ctx, out_tensor, capacity):
+    """Enqueues a copy of the records into a device tensor of
+    n_rep * capacity * 48 bytes (no synchronisation)."""
+    n = C.c_int64(0)
+    _check(lib().kmc_observables(ctx, C.c_void_p(out_tensor.data_ptr()), capacity,
+                                 C.byref(n), F_DEVICE_OUT), ctx)
+    return n.value
+
+
+def kmc_backward_score(ctx, n_rep, n_bins, out_tensor=None):
+    """Score bins [n_rep, n_bins, 2] of the last checkpointed run.  With a
+    device tensor the result is written there asynchronously."""
+    if out_tensor is not None:
+        _check(lib().kmc_backward_score(ctx, C.c_void_p(out_tensor.data_ptr()), n_bins,
+                                        F_DEVICE_OUT), ctx)
+        return out_tensor
+    out = np.zeros((n_rep, n_bins, 2))
+    _check(lib().kmc_backward_score(ctx, _ptr(out), n_bins, 0), ctx)
+    return out
+
+
+def kmc_get_spins(ctx, replica, L):
+    out = np.zeros((L, L), np.int8)
+    _check(lib().kmc_get_spins(ctx, replica, _ptr(out)), ctx)
+    return out
+
+
+def kmc_get_domain_state(ctx, replica):
+    nd = C.c_int32(0)
+    _check(lib().kmc_get_info(ctx, replica, None, C.byref(nd)), ctx)
+    s, c = np.zeros(nd.value), np.zeros(nd.value)
+    e = np.zeros(nd.value, np.int64)
+    _check(lib().kmc_get_domain_state(ctx, replica, _ptr(s), _ptr(c), _ptr(e)), ctx)
+    return s, c, e
+
+
+def kmc_destroy(ctx):
+    if ctx:
+        lib().kmc_destroy(ctx)
+
+
+class Lattice:
+    """Owns one libkmc context: a batch of replicas on the current GPU."""
+
+    def __init__(self, descs, seed, given_spins=None, stream=None, torch_alloc=True):
+        if torch_alloc:
+            use_torch_allocator()
+        self.descs = [dict(d) for d in descs]
+        self.n_rep = len(descs)
+        self.ctx = kmc_init_lattice(descs, seed, given_spins, stream)
+
+    def run(self, n_sweeps, record_every=1, flags=0):
+        kmc_run_schedule(self.ctx, n_sweeps, record_every, flags)
+
+    def records(self):
+        return kmc_observables(self.ctx, self.n_rep)
+
+    def spins(self, replica=0):
+        return kmc_get_spins(self.ctx, replica, self.descs[replica]["L"])
+
+    def domain_state(self, replica=0):
+        return kmc_get_domain_state(self.ctx, replica)
+
+    def score(self, n_bins, out_tensor=None):
+        return kmc_backward_score(self.ctx, self.n_rep, n_bins, out_tensor)
+
+    def close(self):
+        if self.ctx:
+            kmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,99 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libkmc.so loads and exports every call declared in include/kmc.h;
+* its host-built rate table is bit-equal to the oracle's (both are computed
+  with the host libm exp; they share no code);
+* invalid descriptors are rejected with KMC_EINVAL before any device call.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kmc():
+    from paper_1403_4674_amd import kmc as k
+    if not os.path.exists(k.LIB_PATH):
+        from paper_1403_4674_amd import build
+        build.build()
+    return k
+
+
+def declared_calls():
+    with open(os.path.join(ROOT, "include", "kmc.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(kmc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call(kmc):
+    names = declared_calls()
+    assert "kmc_init_lattice" in names and "kmc_backward_score" in names
+    L = kmc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(kmc.exported_symbols()) == names
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_rate_table_bit_equal_to_oracle(kmc, oracle_lib, model):
+    rng = np.random.default_rng(3)
+    cases = [(1.0, 0.0, 2.5), (1.0, 0.0, 2.269), (1.0, 0.0, 1.5)]
+    cases += [(float(a), float(b), float(c)) for a, b, c in
+              zip(rng.uniform(-2, 2, 40), rng.uniform(-1, 1, 40), rng.uniform(0.3, 5, 40))]
+    for J, h, T in cases:
+        a = kmc.kmc_rate_table(J, h, T, model)
+        b = oracle_lib.rates(J, h, T, model)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), (J, h, T)
+
+
+def test_rate_table_rejects_bad_input(kmc):
+    with pytest.raises(kmc.KmcError):
+        kmc.kmc_rate_table(1.0, 0.0, 0.0)
+    with pytest.raises(kmc.KmcError):
+        kmc.kmc_rate_table(1.0, 0.0, 1.0, rate_model=7)
+
+
+BAD = [
+    dict(L=16, tile=6, T=2.0),    # tile not a multiple of 4
+    dict(L=24, tile=8, T=2.0),    # L/tile odd
+    dict(L=16, tile=16, T=2.0),   # one tile per dimension
+    dict(L=20, tile=8, T=2.0),    # L not a multiple of tile
+    dict(L=256, tile=128, T=2.0), # tile above 64
+    dict(L=16, tile=8, T=0.0),    # T must be positive
+    dict(L=16, tile=8, T=float("nan")),
+    dict(L=16, tile=8, T=2.0, steps_per_visit=-1),
+    dict(L=16, tile=8, T=2.0, rate_model=3),
+    dict(L=16, tile=8, T=2.0, schedule=5),
+    dict(L=16, tile=8, T=2.0, init=9),
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_init_rejects_invalid_descriptor(kmc, bad):
+    arr = kmc.make_descs([dict(L=16, tile=8, T=2.0), bad])
+    ctx = C.c_void_p()
+    st = kmc.lib().kmc_init_lattice(C.byref(ctx), arr, 2, C.c_uint64(1), None, None)
+    assert st == kmc.KMC_EINVAL and not ctx.value
+
+
+def test_calls_reject_null_context(kmc):
+    L = kmc.lib()
+    assert L.kmc_run_schedule(None, 1, 1, 0) == kmc.KMC_EINVAL
+    assert L.kmc_backward_score(None, None, 0, 0) == kmc.KMC_EINVAL
+    assert L.kmc_get_spins(None, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_last_error(None) == b"null context"
+    L.kmc_destroy(None)
+
+
+def test_allocator_hooks_must_come_in_pairs(kmc):
+    L = kmc.lib()
+    alloc = kmc._ALLOC_FN(lambda n, u: None)
+    assert L.kmc_set_device_allocator(alloc, C.cast(None, kmc._FREE_FN), None) == kmc.KMC_EINVAL
+    assert L.kmc_set_device_allocator(C.cast(None, kmc._ALLOC_FN),
+                                      C.cast(None, kmc._FREE_FN), None) == kmc.KMC_OK

@@ -1,0 +1,136 @@
+"""GPU vs oracle parity through the C-ABI (needs an MI355X).
+
+Lattice states, per-domain and total event counts, step counts and the
+integer observables must be bit-identical to the serial oracle; simulated
+time (FP64 sums of -ln(u)/R) within 1e-12 relative.  Sizes: the full
+16x16 workload, the 1024^2 and 4096^2 lattices at their real domain shapes
+for a prefix of sweeps, and ragged batches of the batched workload.
+"""
+import numpy as np
+import pytest
+
+from paper_1403_4674_amd import kmc, workloads
+from tests.gpu_helpers import assert_records_equal, assert_replica_equal, oracle_for, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    return torch
+
+
+def run_both(kmco, descs, seed, sweeps, record_every=1, flags=0, given=None, chunks=None):
+    lat = kmc.Lattice(descs, seed, given_spins=given)
+    for n in (chunks or [sweeps]):
+        lat.run(n, record_every, flags)
+    g_rec = lat.records()
+    oras, o_recs = [], []
+    for rho, d in enumerate(descs):
+        o = oracle_for(kmco, d, seed, rho, None if given is None else given[rho])
+        o_recs.append(o.run(sweeps, record_every) if not chunks else
+                      np.concatenate([o.run(n, record_every) for n in chunks]))
+        oras.append(o)
+    return lat, g_rec, oras, o_recs
+
+
+def test_single_16_full_run(torch_cuda, oracle_lib):
+    cases, run = workloads.single_16()
+    for seed, descs in cases:
+        say(f"16x16 seed {seed} {run['sweeps']} sweeps")
+        lat, g, oras, o = run_both(oracle_lib, descs, seed, run["sweeps"], run["record_every"])
+        assert_replica_equal(lat, 0, oras[0], g[0], o[0], f"seed {seed}")
+        lat.close()
+
+
+@pytest.mark.parametrize("flags", [kmc.F_PERSISTENT, kmc.F_GRAPH])
+def test_paths_are_bit_identical(torch_cuda, oracle_lib, flags):
+    descs = [dict(L=16, tile=8, T=2.5, steps_per_visit=64),
+             dict(L=24, tile=12, T=1.9, h=0.2),
+             dict(L=32, tile=8, T=3.1, h=-0.1, steps_per_visit=10),
+             dict(L=64, tile=16, T=2.2, h=0.05),
+             dict(L=128, tile=64, T=2.6, steps_per_visit=700),
+             dict(L=48, tile=24, T=1.6, h=0.4)]
+    say(f"ragged batch, flags {flags}")
+    a = kmc.Lattice(descs, 77)
+    b = kmc.Lattice(descs, 77)
+    a.run(37, 4)
+    b.run(37, 4, flags)
+    ra, rb = a.records(), b.records()
+    for f in ("sweep", "M", "B", "events", "steps"):
+        assert np.array_equal(ra[f], rb[f]), f
+    np.testing.assert_allclose(ra["t"], rb["t"], rtol=1e-13)
+    for rho in range(len(descs)):
+        assert np.array_equal(a.spins(rho), b.spins(rho)), rho
+    # and against the oracle, every replica
+    for rho, d in enumerate(descs):
+        o = oracle_for(oracle_lib, d, 77, rho)
+        orec = o.run(37, 4)
+        assert_replica_equal(b, rho, o, rb[rho], orec, f"replica {rho}")
+
+
+@pytest.mark.parametrize("T", [1.5, 2.269, 3.0])
+def test_single_1024_prefix(torch_cuda, oracle_lib, T):
+    seed, descs, _ = workloads.single_1024(T)
+    say(f"1024^2 T={T}, 3 sweeps")
+    lat, g, oras, o = run_both(oracle_lib, descs, seed, 3, 1)
+    assert_replica_equal(lat, 0, oras[0], g[0], o[0], f"1024 T={T}")
+
+
+def test_quench_4096_prefix(torch_cuda, oracle_lib):
+    seed, descs, _ = workloads.quench_4096()
+    say("4096^2 T=1.5, 1 sweep at N_I=4096")
+    lat, g, oras, o = run_both(oracle_lib, descs, seed, 1, 1)
+    assert_replica_equal(lat, 0, oras[0], g[0], o[0], "4096 quench")
+
+
+def test_quench_4096_short_visits(torch_cuda, oracle_lib):
+    seed, descs, _ = workloads.quench_4096()
+    descs = [dict(descs[0], steps_per_visit=64)]
+    say("4096^2 T=1.5, 4 sweeps at N_I=64")
+    lat, g, oras, o = run_both(oracle_lib, descs, seed, 4, 2)
+    assert_replica_equal(lat, 0, oras[0], g[0], o[0], "4096 N_I=64")
+
+
+def test_batched_sample_persistent(torch_cuda, oracle_lib):
+    seed, descs, _ = workloads.batched_4096(n=96)
+    say("96 ragged replicas, persistent, 12 sweeps")
+    lat, g, oras, o = run_both(oracle_lib, descs, seed, 12, 3, kmc.F_PERSISTENT)
+    Ls = {d["L"] for d in descs}
+    assert Ls == {16, 24, 32, 48, 64, 128}
+    for rho in range(len(descs)):
+        assert_replica_equal(lat, rho, oras[rho], g[rho], o[rho], f"replica {rho}")
+
+
+@pytest.mark.parametrize("variant", ["palindrome", "barker", "given", "all_up"])
+def test_schedule_rate_and_init_variants(torch_cuda, oracle_lib, variant):
+    d = dict(L=32, tile=8, T=2.1, h=0.1, steps_per_visit=50)
+    given = None
+    if variant == "palindrome":
+        d["schedule"] = kmc.SCHED_PALINDROME
+    elif variant == "barker":
+        d["rate_model"] = kmc.RATE_BARKER
+    elif variant == "all_up":
+        d["init"] = kmc.INIT_ALL_UP
+    else:
+        d["init"] = kmc.INIT_GIVEN
+        rng = np.random.default_rng(8)
+        given = [np.where(rng.random((32, 32)) < 0.3, 1, -1).astype(np.int8)]
+    say(f"variant {variant}")
+    lat, g, oras, o = run_both(oracle_lib, [d], 11, 25, 5, given=given)
+    assert_replica_equal(lat, 0, oras[0], g[0], o[0], variant)
+
+
+def test_resume_and_determinism(torch_cuda, oracle_lib):
+    descs = [dict(L=32, tile=16, T=2.4, h=0.05), dict(L=16, tile=4, T=2.0)]
+    say("resume: 7 + 13 sweeps vs 20")
+    lat, g, oras, o = run_both(oracle_lib, descs, 5, 20, 1, chunks=[7, 13])
+    for rho in range(2):
+        assert_replica_equal(lat, rho, oras[rho], g[rho], o[rho], f"resume {rho}")
+    b = kmc.Lattice(descs, 5)
+    b.run(20, 1)
+    rb = b.records()
+    for f in ("M", "B", "events"):
+        assert np.array_equal(rb[f], g[f])
