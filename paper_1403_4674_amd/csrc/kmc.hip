@@ -57,7 +57,8 @@ struct kmc_ctx {
     int64_t spin_bytes = 0;
     int32_t n_dom = 0;
     int32_t n_tasks = 0, n_tasks32 = 0;
-    int32_t n_order32 = 0, n_order64 = 0;
+    // persistent queues per row-mask width: [team..., solo...]
+    int32_t n_team[2] = {0, 0}, n_solo[2] = {0, 0};
     int n_phase = 4;
 
     Rep *d_reps = nullptr;
@@ -180,6 +181,26 @@ kmc_status rate_table(double J, double h, double T, int32_t model, uint64_t r[10
     return KMC_OK;
 }
 
+// Expected work of one sweep of a replica, for ordering the persistent
+// queues (longest first); results do not depend on it.  Events cost about
+// six null ticks; the event fraction grows with T (piecewise linear fit of
+// equilibrium Metropolis runs at h = 0).
+double sweep_cost(const Rep &rp, const kmc_replica_desc &d) {
+    static const double Tk[] = {1.0, 1.5, 2.269, 2.5, 3.0, 3.5, 5.0};
+    static const double pk[] = {0.001, 0.013, 0.20, 0.32, 0.46, 0.55, 0.70};
+    double p = pk[6];
+    if (d.T <= Tk[0]) {
+        p = pk[0];
+    } else {
+        for (int i = 1; i < 7; ++i)
+            if (d.T <= Tk[i]) {
+                p = pk[i - 1] + (pk[i] - pk[i - 1]) * (d.T - Tk[i - 1]) / (Tk[i] - Tk[i - 1]);
+                break;
+            }
+    }
+    return (double)rp.NI * rp.ND * rp.visits * (1.0 + 6.0 * p);
+}
+
 void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     auto bad = [&](const char *why) {
         fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": " + why);
@@ -211,7 +232,8 @@ KParams params(kmc_ctx *c) {
     K.order = c->d_order;
     K.bins = nullptr;
     K.n_rep = c->n_rep;
-    K.n_order = 0;
+    K.n_team = 0;
+    K.n_solo = 0;
     K.n_bins = 0;
     K.seed = c->seed;
     K.write_records = 1;
@@ -246,21 +268,24 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps) 
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
     const int waves = kmcdev::kWavesPerPersistentGroup;
+    int32_t off = 0;
     for (int g = 0; g < 2; ++g) {
-        const int n = g == 0 ? c->n_order32 : c->n_order64;
-        if (!n) continue;
-        K.order = c->d_order + (g == 0 ? 0 : c->n_order32);
-        K.n_order = n;
-        const int groups = std::min((n + waves - 1) / waves, cus * 8);
+        const int nt = c->n_team[g], ns = c->n_solo[g];
+        if (!nt && !ns) continue;
+        K.order = c->d_order + off;
+        K.n_team = nt;
+        K.n_solo = ns;
+        off += nt + ns;
+        const int groups = std::max(1, std::min(nt + (ns + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         if (g == 0)
             hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
                                dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
-                               n_sweeps, 0);
+                               n_sweeps);
         else
             hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
                                dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
-                               n_sweeps, 1);
+                               n_sweeps);
     }
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "persistent launch");
@@ -382,10 +407,12 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             if (q.schedule == KMC_SCHED_PALINDROME) c->n_phase = 8;
             if (q.init == KMC_INIT_GIVEN) any_given = true;
             Rates &R = c->rates[rho];
+            std::memset(&R, 0, sizeof(R));
             double gJ[10], gh[10];
             if (rate_table(q.J, q.h, q.T, q.rate_model, R.r, R.w, gJ, gh) != KMC_OK)
                 fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": rate table");
             for (int k = 0; k < 10; ++k) {
+                R.inv_r[k] = R.r[k] ? (float)(1.0 / (double)R.r[k]) : 0.0f;
                 R.gJ[k] = gJ[k];
                 R.gh[k] = gh[k];
                 R.aJ[k] = R.w[k] * gJ[k];
@@ -407,18 +434,27 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();
             }
         c->n_tasks = (int32_t)task_rep.size();
-        // persistent queues: costliest replica first within each group
+        // persistent queues: per row-mask width, replicas with at least four
+        // domains per colour and a large sweep run as a workgroup team, the
+        // rest on single wavefronts; each list costliest first
         std::vector<int32_t> order;
         for (int pass = 0; pass < 2; ++pass) {
-            std::vector<int32_t> g;
-            for (int rho = 0; rho < n_rep; ++rho)
-                if ((c->reps[rho].B > 32) == (pass == 1)) g.push_back(rho);
-            std::stable_sort(g.begin(), g.end(), [&](int a, int b) {
-                const Rep &x = c->reps[a], &y = c->reps[b];
-                return (int64_t)x.NI * x.ND * x.visits > (int64_t)y.NI * y.ND * y.visits;
-            });
-            (pass == 0 ? c->n_order32 : c->n_order64) = (int32_t)g.size();
-            order.insert(order.end(), g.begin(), g.end());
+            std::vector<int32_t> team, solo;
+            for (int rho = 0; rho < n_rep; ++rho) {
+                const Rep &rp = c->reps[rho];
+                if ((rp.B > 32) != (pass == 1)) continue;
+                const int64_t ticks = (int64_t)rp.NI * rp.ND * rp.visits;
+                ((rp.ND / 4 >= 4 && ticks >= 8192) ? team : solo).push_back(rho);
+            }
+            auto by_cost = [&](int a, int b) {
+                return sweep_cost(c->reps[a], c->desc[a]) > sweep_cost(c->reps[b], c->desc[b]);
+            };
+            std::stable_sort(team.begin(), team.end(), by_cost);
+            std::stable_sort(solo.begin(), solo.end(), by_cost);
+            c->n_team[pass] = (int32_t)team.size();
+            c->n_solo[pass] = (int32_t)solo.size();
+            order.insert(order.end(), team.begin(), team.end());
+            order.insert(order.end(), solo.begin(), solo.end());
         }
 
         c->d_reps = alloc_n<Rep>(c, n_rep);

@@ -48,6 +48,8 @@ constexpr int kWavesPerPersistentGroup = 4;
 
 struct Rates {
     uint64_t r[10];                       // Q32 rates
+    float inv_r[10];                      // 1/r (0 for r = 0), for the member index
+    float pad_inv[6];
     double w[10], aJ[10], ah[10];         // w, w*dlnw/dJ, w*dlnw/dh
     double gJ[10], gh[10];                // dlnw/dJ, dlnw/dh
 };
@@ -83,8 +85,9 @@ struct Ctl {
     int64_t run_done;   // sweeps done in the current run
     int64_t rec_base;   // records written before the current run
     int64_t rec_every;  // record interval of the current run
-    int64_t queue;      // persistent work queue head
-    int64_t pad[3];
+    int64_t queue;      // persistent team-queue head
+    int64_t queue2;     // persistent solo-queue head
+    int64_t pad[2];
 };
 
 struct KParams {
@@ -96,10 +99,11 @@ struct KParams {
     Record *rec;
     Ctl *ctl;
     const int32_t *task_rep;  // phase task -> replica
-    const int32_t *order;     // persistent queue order (costliest first)
+    const int32_t *order;     // persistent queue: team replicas, then solo ones
     double *bins;             // score bins [n_rep][n_bins][2]
     int32_t n_rep;
-    int32_t n_order;          // persistent queue length
+    int32_t n_team;           // persistent queue: replicas run by a workgroup
+    int32_t n_solo;           // persistent queue: replicas run by a wavefront
     int32_t n_bins;
     uint64_t seed;
     int32_t write_records;
@@ -181,6 +185,55 @@ __device__ inline int phase_colour(const Rep &rp, uint64_t seed, uint32_t rho,
 }
 
 // ------------------------------------------------------------ wave helpers
+//
+// Lane-to-lane moves inside the event chain use DPP (data-parallel
+// primitives: a VALU operand modifier, no LDS round trip).  Out-of-range
+// source lanes and rows excluded by the row mask read 0.
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+constexpr int kWaveShr1 = 0x138;   // lane i <- lane i-1
+constexpr int kWaveShl1 = 0x130;   // lane i <- lane i+1
+constexpr int kRowShr = 0x110;     // + n: lane i <- lane i-n inside a row of 16
+constexpr int kRowBcast15 = 0x142; // lane 15 of each row -> the next row
+constexpr int kRowBcast31 = 0x143; // lane 31 -> rows 2 and 3
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_any(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t lo = dpp<CTRL>((uint32_t)v);
+        const uint32_t hi = dpp<CTRL>((uint32_t)(v >> 32));
+        return ((T)hi << 32) | lo;
+    } else {
+        return (T)dpp<CTRL>((uint32_t)v);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ uint32_t scan64(uint32_t v) {
+    v += dpp<kRowShr + 1>(v);
+    v += dpp<kRowShr + 2>(v);
+    v += dpp<kRowShr + 4>(v);
+    v += dpp<kRowShr + 8>(v);
+    v += dpp<kRowBcast15, 0xA>(v);
+    v += dpp<kRowBcast31, 0xC>(v);
+    return v;
+}
+
+// Inclusive prefix sum over lanes 0..15 (64-bit values).
+__device__ __forceinline__ uint64_t scan16_dpp(uint64_t v) {
+    v += dpp_any<kRowShr + 1>(v);
+    v += dpp_any<kRowShr + 2>(v);
+    v += dpp_any<kRowShr + 4>(v);
+    v += dpp_any<kRowShr + 8>(v);
+    return v;
+}
+
+// Sum over lanes 0..15 of a double, returned in every lane.
+__device__ __forceinline__ double rowsum16_f64(double v, int lane);
 
 __device__ __forceinline__ uint32_t rdl32(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
@@ -190,6 +243,22 @@ __device__ __forceinline__ uint64_t rdl64(uint64_t v, int lane) {
     const uint32_t lo = rdl32((uint32_t)v, lane);
     const uint32_t hi = rdl32((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double rowsum16_f64(double v, int lane) {
+    (void)lane;
+    uint64_t b = __double_as_longlong(v);
+#pragma unroll
+    for (int sft = 1; sft < 16; sft <<= 1) {
+        const uint64_t t = sft == 1 ? dpp_any<kRowShr + 1>(b)
+                         : sft == 2 ? dpp_any<kRowShr + 2>(b)
+                         : sft == 4 ? dpp_any<kRowShr + 4>(b)
+                                    : dpp_any<kRowShr + 8>(b);
+        b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(t));
+    }
+    const uint64_t tot = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), 15) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 15);
+    return __longlong_as_double(tot);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
@@ -251,6 +320,12 @@ __device__ __forceinline__ int popc(MT m) {
         return __popc(m);
 }
 
+// Number of set bits of the wave-uniform mask m below this lane.
+__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Position of the n-th (0-based) set bit of m; n < popc(m).
 template <typename MT>
 __device__ __forceinline__ int nth_set_bit(MT m, int n) {
@@ -300,9 +375,9 @@ template <typename MT>
 __device__ __forceinline__ Planes<MT> neighbour_planes(MT S, MT top, MT bot,
                                                       MT hl, MT hr, int B,
                                                       MT VM, int lane) {
-    MT U = __shfl_up(S, 1);
+    MT U = dpp_any<kWaveShr1>(S);
     if (lane == 0) U = top;
-    MT D = __shfl_down(S, 1);
+    MT D = dpp_any<kWaveShl1>(S);
     if (lane == B - 1) D = bot;
     const MT Lf = ((S << 1) | hl) & VM;
     const MT Rt = ((S >> 1) | (hr << (B - 1))) & VM;
@@ -396,42 +471,46 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     }
     Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
 
-    // ---- class counts: per-row popcounts, reduced two classes per word
+    // ---- class counts: per-row popcounts, two classes per 32-bit word
     uint32_t n_lane = 0;  // lanes 0..9: n_c
 #pragma unroll
     for (int c = 0; c < 10; c += 2) {
         const uint32_t a = popc(class_mask<MT>(c, S, P, VM));
         const uint32_t b = popc(class_mask<MT>(c + 1, S, P, VM));
-        const uint32_t s = wave_sum_u32(a | (b << 16));
-        if (lane == c) n_lane = s & 0xFFFFu;
-        if (lane == c + 1) n_lane = s >> 16;
+        const uint32_t tot = rdl32(scan64(a | (b << 16)), 63);
+        if (lane == c) n_lane = tot & 0xFFFFu;
+        if (lane == c + 1) n_lane = tot >> 16;
     }
     const uint64_t r_lane = lane < 10 ? rt->r[lane] : 0;
+    const float inv_lane = lane < 10 ? rt->inv_r[lane] : 0.0f;
+    const int lane3 = 3 * lane;
     uint64_t W = (uint64_t)n_lane * r_lane;
-    uint64_t Pinc = scan16(W, lane);
+    uint64_t Pinc = scan16_dpp(W);
     uint64_t R = rdl64(Pinc, 9);
 
-    double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0;
+    double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
     if constexpr (SCORE) {
         if (lane < 10) {
             w_lane = rt->w[lane];
             aJ_lane = rt->aJ[lane];
             ah_lane = rt->ah[lane];
+            gJ_lane = rt->gJ[lane];
+            gh_lane = rt->gh[lane];
         }
     }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
-    double clk_sum = dom->clk_sum, clk_comp = dom->clk_comp;
-    uint32_t m_null = 0;  // null ticks since the last event (score)
+    double clk_sum = 0.0, clk_comp = 0.0;  // this lane's events' residence times
+    uint32_t m_null = 0;                   // null ticks since the last event (score)
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
 
     auto null_score = [&](uint32_t m) {
         // d ln(1 - R_w/n_d)/d theta per null tick, times m
         const double nl = (double)n_lane;
-        const double Rw = sum16_f64(nl * w_lane);
-        const double RJ = sum16_f64(nl * aJ_lane);
-        const double Rh = sum16_f64(nl * ah_lane);
+        const double Rw = rowsum16_f64(nl * w_lane, lane);
+        const double RJ = rowsum16_f64(nl * aJ_lane, lane);
+        const double Rh = rowsum16_f64(nl * ah_lane, lane);
         const double den = (double)nd - Rw;
         if (den > 0.0) {
             out.sJ += (double)m * (-RJ / den);
@@ -470,52 +549,72 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             const uint64_t xe = rdl64(x, e);
             if (lane == e) Rb = R;
 
-            // rate class: first c with xe < P_c
+            // rate class: first c with xe < P_c; member index j =
+            // floor((xe - P_{c-1}) / r_c), formed in every class lane at
+            // once: FP32 estimate (error < 1) and one exact integer correction
             const int c = __ffsll((long long)__ballot(lane < 10 && xe < Pinc)) - 1;
-            const uint64_t Pc = rdl64(Pinc - W, c);
-            const uint64_t rc = rdl64(r_lane, c);
-            const uint64_t a = xe - Pc;
-            uint64_t j = (uint64_t)floor((double)a / (double)rc);
-            if (j * rc > a)
-                --j;
-            else if ((j + 1) * rc <= a)
-                ++j;
+            const uint64_t Pexc = Pinc - W;
+            const uint64_t a = xe >= Pexc ? xe - Pexc : 0;
+            const float af = (float)(uint32_t)(a >> 32) * 4294967296.0f + (float)(uint32_t)a;
+            const uint32_t j0 = (uint32_t)(af * inv_lane);
+            const uint64_t tj = (uint64_t)j0 * r_lane;
+            const uint32_t jl = j0 - (tj > a ? 1u : 0u) + (tj + r_lane <= a ? 1u : 0u);
+            const uint32_t j = rdl32(jl, c);
 
             if constexpr (SCORE) {
                 if (m_null) null_score(m_null);
-                out.sJ += rt->gJ[c];
-                out.sh += rt->gh[c];
+                out.sJ += __longlong_as_double((long long)rdl64(__double_as_longlong(gJ_lane), c));
+                out.sh += __longlong_as_double((long long)rdl64(__double_as_longlong(gh_lane), c));
             }
             m_null = 0;
 
-            // member j of class c in ascending row-major order
+            // member j of class c in ascending row-major order: the row by a
+            // 64-lane scan of per-row counts, the column by counting the
+            // row's members below each lane (mbcnt)
             const MT cm = class_mask<MT>(c, S, P, VM);
             const uint32_t cnt = (uint32_t)popc(cm);
-            const uint32_t incl = wave_incl_scan(cnt, lane);
-            const int ys = __ffsll((long long)__ballot(incl > (uint32_t)j)) - 1;
-            const int jl = (int)((uint32_t)j - (incl - cnt));
-            const int bitpos = nth_set_bit<MT>(cm, jl < 0 ? 0 : jl);
-            const int xs = (int)rdl32((uint32_t)bitpos, ys);
+            const uint32_t incl = scan64(cnt);
+            const int ys = __ffsll((long long)__ballot(incl > j)) - 1;
+            const uint32_t jr = j - rdl32(incl - cnt, ys);
+            uint64_t row = (uint64_t)rdl32((uint32_t)cm, ys);
+            if constexpr (sizeof(MT) == 8) row |= (uint64_t)rdl32((uint32_t)(cm >> 32), ys) << 32;
+            const int xs = __ffsll((long long)(__ballot(bits_below_lane(row) == jr) & row)) - 1;
 
-            // class changes of the flipped site and its in-tile neighbours
+            // class changes of the flipped site and its in-tile neighbours,
+            // as packed 3-bit per-class tallies (10 classes in 30 bits)
             const bool up = c >= 5;
             const int k = up ? c - 5 : c;
             const int delta = up ? -1 : 1;
+            const int xl = xs > 0 ? xs - 1 : xs, xr = xs < B - 1 ? xs + 1 : xs;
             const int cls_mid = class_at<MT>(S, P, xs);
-            const int cls_l = xs > 0 ? class_at<MT>(S, P, xs - 1) : 0;
-            const int cls_r = xs < B - 1 ? class_at<MT>(S, P, xs + 1) : 0;
-            const int cu = ys > 0 ? (int)rdl32((uint32_t)cls_mid, ys - 1) : -100;
-            const int cd = ys < B - 1 ? (int)rdl32((uint32_t)cls_mid, ys + 1) : -100;
-            const int cl = xs > 0 ? (int)rdl32((uint32_t)cls_l, ys) : -100;
-            const int cr = xs < B - 1 ? (int)rdl32((uint32_t)cls_r, ys) : -100;
-            int dn = (lane == (up ? c - 5 : c + 5)) - (lane == c);
-            dn += (lane == cu + delta) - (lane == cu);
-            dn += (lane == cd + delta) - (lane == cd);
-            dn += (lane == cl + delta) - (lane == cl);
-            dn += (lane == cr + delta) - (lane == cr);
-            n_lane = (uint32_t)((int)n_lane + dn);
+            const int cls_l = class_at<MT>(S, P, xl);
+            const int cls_r = class_at<MT>(S, P, xr);
+            uint32_t add = 1u << (3 * (up ? c - 5 : c + 5));
+            uint32_t sub = 1u << (3 * c);
+            if (ys > 0) {
+                const int q = (int)rdl32((uint32_t)cls_mid, ys - 1);
+                sub += 1u << (3 * q);
+                add += 1u << (3 * (q + delta));
+            }
+            if (ys < B - 1) {
+                const int q = (int)rdl32((uint32_t)cls_mid, ys + 1);
+                sub += 1u << (3 * q);
+                add += 1u << (3 * (q + delta));
+            }
+            if (xs > 0) {
+                const int q = (int)rdl32((uint32_t)cls_l, ys);
+                sub += 1u << (3 * q);
+                add += 1u << (3 * (q + delta));
+            }
+            if (xs < B - 1) {
+                const int q = (int)rdl32((uint32_t)cls_r, ys);
+                sub += 1u << (3 * q);
+                add += 1u << (3 * (q + delta));
+            }
+            if (lane < 10)
+                n_lane = n_lane + ((add >> lane3) & 7u) - ((sub >> lane3) & 7u);
             W = (uint64_t)n_lane * r_lane;
-            Pinc = scan16(W, lane);
+            Pinc = scan16_dpp(W);
             R = rdl64(Pinc, 9);
 
             if (lane == ys) S ^= (MT)1 << xs;
@@ -526,19 +625,28 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             ++out.events;
             pos = e + 1;
         }
-        // residence times -ln(u)/R_w of this batch's events
-        if (__ballot(Rb != 0)) {
-            double dt = 0.0;
-            if (Rb) {
-                const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
-                const double u = (double)(u53 + 1) * 0x1p-53;
-                dt = -log(u) * 4294967296.0 / (double)Rb;
-            }
-            neumaier_add(clk_sum, clk_comp, wave_sum_f64(dt));
+        // residence times -ln(u)/R_w of this batch's events, kept per lane
+        if (Rb) {
+            const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
+            const double u = (double)(u53 + 1) * 0x1p-53;
+            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / (double)Rb);
         }
     }
     if constexpr (SCORE) {
         if (m_null) null_score(m_null);
+    }
+    {
+        double cs = clk_sum, cc = clk_comp;
+        cs = wave_sum_f64(cs);
+        cc = wave_sum_f64(cc);
+        if (lane == 0) {
+            double ds = dom->clk_sum, dc = dom->clk_comp;
+            neumaier_add(ds, dc, cs);
+            neumaier_add(ds, dc, cc);
+            dom->clk_sum = ds;
+            dom->clk_comp = dc;
+            dom->events += out.events;
+        }
     }
 
     // ---- write the tile back through LDS
@@ -552,11 +660,6 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         const int row = q / B4, c4 = q - row * B4;
         *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
             *reinterpret_cast<const uint32_t *>(tile + row * B + 4 * c4);
-    }
-    if (lane == 0) {
-        dom->clk_sum = clk_sum;
-        dom->clk_comp = clk_comp;
-        dom->events += out.events;
     }
     wave_sync_lds();  // LDS reads of the write-back finish before reuse
     return out;
@@ -645,7 +748,10 @@ __global__ void k_advance(Ctl *ctl, int64_t n) {
     ctl->run_done += n;
 }
 
-__global__ void k_reset_queue(Ctl *ctl) { ctl->queue = 0; }
+__global__ void k_reset_queue(Ctl *ctl) {
+    ctl->queue = 0;
+    ctl->queue2 = 0;
+}
 
 __global__ void k_set_ctl(Ctl *ctl, int64_t run_done, int64_t rec_base,
                           int64_t rec_every, int64_t sweep) {
@@ -653,83 +759,167 @@ __global__ void k_set_ctl(Ctl *ctl, int64_t run_done, int64_t rec_base,
     ctl->rec_base = rec_base;
     ctl->rec_every = rec_every;
     ctl->queue = 0;
+    ctl->queue2 = 0;
     ctl->sweep = sweep;
 }
 
-// Persistent batched form: each wavefront takes replicas from a queue
-// (costliest first) and runs all n_sweeps sweeps of each, every colour
-// phase and every domain in order; nothing is shared between wavefronts.
+// Closes a record interval of replica rho after sweep w: adds the score to
+// its bin and writes the record when due (lane 0 writes).
+template <bool SCORE>
+__device__ inline void close_interval(const KParams &K, const Rep &rp, int rho, uint32_t w,
+                                      int64_t done, int64_t rec_every, int64_t rec_base,
+                                      const RepAcc &acc, double sJ, double sh, int lane) {
+    __threadfence();
+    if constexpr (SCORE) {
+        if (lane == 0) {
+            const int64_t bin = (done - 1) / rec_every;
+            double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
+            b[0] += sJ;
+            b[1] += sh;
+        }
+    }
+    if (K.write_records && done % rec_every == 0) {
+        const double t = replica_time(K, rp, lane);
+        if (lane == 0) {
+            const int64_t k = rec_base + done / rec_every - 1;
+            Record r;
+            r.sweep = (int64_t)w + 1;
+            r.M = acc.M;
+            r.B = acc.B;
+            r.events = acc.events;
+            r.steps = ((int64_t)w + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
+            r.t = t;
+            K.rec[k * K.n_rep + rho] = r;
+        }
+    }
+}
+
+struct TeamShared {
+    int64_t dM[kWavesPerPersistentGroup], dB[kWavesPerPersistentGroup],
+        ev[kWavesPerPersistentGroup];
+    double sJ[kWavesPerPersistentGroup], sh[kWavesPerPersistentGroup];
+};
+
+// All n_sweeps sweeps of replica rho, run by `nw` wavefronts (1, or the 4 of
+// the workgroup).  In each colour phase wavefront `wave` takes the phase's
+// domains wave, wave + nw, ...; with a team a workgroup barrier separates the
+// phases (domains of one colour never touch, so the split changes no result).
+template <typename MT, bool SCORE>
+__device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lane,
+                            uint8_t *lds, TeamShared *ts, int64_t sweep0,
+                            int64_t run_done0, int64_t n_sweeps, int64_t rec_every,
+                            int64_t rec_base) {
+    const Rep rp = K.reps[rho];
+    RepAcc acc = K.acc[rho];  // with a team, wavefront 0 keeps the totals
+    int64_t dM = 0, dB = 0, ev = 0;
+    double sJ = 0.0, sh = 0.0;
+    const int nphase = rp.sched == 1 ? 8 : 4;
+    const int per_colour = rp.ND >> 2;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t w = (uint32_t)(sweep0 + i);
+        for (int p = 0; p < nphase; ++p) {
+            int vis;
+            const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
+            for (int i2 = wave; i2 < per_colour; i2 += nw) {
+                int d, oy, ox;
+                colour_domain(rp, col, i2, &d, &oy, &ox);
+                const VisitOut o = visit_domain<MT, SCORE>(
+                    K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
+                    (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+                dM += o.dM;
+                dB += o.dB;
+                ev += o.events;
+                sJ += o.sJ;
+                sh += o.sh;
+            }
+            if (nw > 1) __syncthreads();
+        }
+        const int64_t done = run_done0 + i + 1;
+        if (done % rec_every == 0 || i + 1 == n_sweeps) {
+            if (nw > 1) {
+                if (lane == 0) {
+                    ts->dM[wave] = dM;
+                    ts->dB[wave] = dB;
+                    ts->ev[wave] = ev;
+                    ts->sJ[wave] = sJ;
+                    ts->sh[wave] = sh;
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    dM = dB = ev = 0;
+                    sJ = sh = 0.0;
+                    for (int q = 0; q < nw; ++q) {
+                        dM += ts->dM[q];
+                        dB += ts->dB[q];
+                        ev += ts->ev[q];
+                        sJ += ts->sJ[q];
+                        sh += ts->sh[q];
+                    }
+                }
+            }
+            if (wave == 0) {
+                acc.M += dM;
+                acc.B += dB;
+                acc.events += ev;
+                close_interval<SCORE>(K, rp, rho, w, done, rec_every, rec_base, acc, sJ, sh,
+                                      lane);
+            }
+            dM = dB = ev = 0;
+            sJ = sh = 0.0;
+            if (nw > 1) __syncthreads();
+        }
+    }
+    if (wave == 0 && lane == 0) K.acc[rho] = acc;
+}
+
+// Persistent batched form.  The launch's queue holds n_team replicas run by
+// a whole workgroup (costliest first), then n_solo replicas run by single
+// wavefronts (costliest first).  Every wavefront leaves once both queues
+// are drained.  One call site keeps the domain process inlined once.
 template <typename MT, bool SCORE>
 __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
-    KParams K, int64_t sweep0, int64_t run_done0, int64_t n_sweeps, int mt64) {
+    KParams K, int64_t sweep0, int64_t run_done0, int64_t n_sweeps) {
     __shared__ __attribute__((aligned(16)))
     uint8_t lds_all[kWavesPerPersistentGroup][kLdsPerWave];
-    uint8_t *lds = lds_all[threadIdx.x >> 6];
+    __shared__ TeamShared ts;
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint8_t *lds = lds_all[wave];
     const int lane = __lane_id();
     const int64_t rec_every = K.ctl->rec_every;
     const int64_t rec_base = K.ctl->rec_base;
+    bool team_phase = true;
     for (;;) {
-        int idx = 0;
-        if (lane == 0)
-            idx = (int)atomicAdd((unsigned long long *)&K.ctl->queue, 1ull);
-        idx = (int)rdl32((uint32_t)idx, 0);
-        if (idx >= K.n_order) return;
-        const int rho = K.order[idx];
-        const Rep rp = K.reps[rho];
-        if ((rp.B > 32) != (mt64 != 0)) continue;  // other template instance
-        RepAcc acc = K.acc[rho];
-        double sJ = 0.0, sh = 0.0;
-        for (int64_t i = 0; i < n_sweeps; ++i) {
-            const uint32_t w = (uint32_t)(sweep0 + i);
-            const int nphase = rp.sched == 1 ? 8 : 4;
-            for (int p = 0; p < nphase; ++p) {
-                int vis;
-                const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
-                const int per_colour = rp.ND >> 2;
-                for (int i2 = 0; i2 < per_colour; ++i2) {
-                    int d, oy, ox;
-                    colour_domain(rp, col, i2, &d, &oy, &ox);
-                    const VisitOut o = visit_domain<MT, SCORE>(
-                        K.spins + rp.spin_off, rp, K.rates + rho, oy, ox,
-                        (uint32_t)d, (uint32_t)vis, w, (uint32_t)rho, K.seed,
-                        K.dom + rp.dom_off + d, lds);
-                    acc.M += o.dM;
-                    acc.B += o.dB;
-                    acc.events += o.events;
-                    sJ += o.sJ;
-                    sh += o.sh;
-                }
+        int rho, me, nw;
+        if (team_phase) {  // workgroup-uniform branch
+            if (threadIdx.x == 0)
+                s_item = (int)atomicAdd((unsigned long long *)&K.ctl->queue, 1ull);
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (it >= K.n_team) {
+                team_phase = false;
+                continue;
             }
-            const int64_t done = run_done0 + i + 1;
-            if (done % rec_every == 0 || i + 1 == n_sweeps) {
-                __threadfence();
-                if constexpr (SCORE) {
-                    if (lane == 0) {
-                        const int64_t bin = (done - 1) / rec_every;
-                        double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
-                        b[0] += sJ;
-                        b[1] += sh;
-                    }
-                    sJ = 0.0;
-                    sh = 0.0;
-                }
-                if (K.write_records && done % rec_every == 0) {
-                    const double t = replica_time(K, rp, lane);
-                    if (lane == 0) {
-                        const int64_t k = rec_base + done / rec_every - 1;
-                        Record r;
-                        r.sweep = (int64_t)w + 1;
-                        r.M = acc.M;
-                        r.B = acc.B;
-                        r.events = acc.events;
-                        r.steps = ((int64_t)w + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
-                        r.t = t;
-                        K.rec[k * K.n_rep + rho] = r;
-                    }
-                }
-            }
+            rho = K.order[it];
+            me = wave;
+            nw = kWavesPerPersistentGroup;
+        } else {
+            int idx = 0;
+            if (lane == 0)
+                idx = (int)atomicAdd((unsigned long long *)&K.ctl->queue2, 1ull);
+            idx = (int)rdl32((uint32_t)idx, 0);
+            if (idx >= K.n_solo) return;
+            rho = K.order[K.n_team + idx];
+            me = 0;
+            nw = 1;
         }
-        if (lane == 0) K.acc[rho] = acc;
+        // wave-uniform: keep them (and all replica data) in scalar registers
+        rho = __builtin_amdgcn_readfirstlane(rho);
+        me = __builtin_amdgcn_readfirstlane(me);
+        nw = __builtin_amdgcn_readfirstlane(nw);
+        run_replica<MT, SCORE>(K, rho, me, nw, lane, lds, &ts, sweep0, run_done0, n_sweeps,
+                               rec_every, rec_base);
     }
 }
 

@@ -109,7 +109,10 @@ def use_torch_allocator():
                 return None
 
         def free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch already torn down
+                pass
 
         _torch_hooks = (_ALLOC_FN(alloc), _FREE_FN(free))
     _check(lib().kmc_set_device_allocator(_torch_hooks[0], _torch_hooks[1], None))
