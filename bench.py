@@ -136,6 +136,18 @@ def cpu_baseline(budget_s):
                        f"{sec:.1f} s")
 
 
+def copy_probe(nbytes):
+    """A plain device copy of known size (PMC byte-counter calibration)."""
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    return nbytes
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,12 +157,17 @@ def main():
     ap.add_argument("--batched-sweeps", type=int, default=40)
     ap.add_argument("--grad-sweeps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--mode", default="all",
+                    choices=["all", "plain", "batched", "backward", "copy"],
+                    help="all: the full line; the others run one part (for profiling)")
+    ap.add_argument("--no-extras", action="store_true", help="same as --mode plain")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method's replicas and domains are "
               "run on a single MI355X here; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.no_extras:
+        args.mode = "plain"
 
     import torch
 
@@ -160,6 +177,20 @@ def main():
     # events are recorded on that same stream
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
+
+    if args.mode == "copy":
+        n = copy_probe(1 << 30)
+        print(json.dumps({"copy_probe_bytes": n}), flush=True)
+        return
+    if args.mode == "batched":
+        b = batched(args, kmc, workloads)
+        print(json.dumps({"batched_site_updates_per_s": b["ticks"] / b["sec"], **b}),
+              flush=True)
+        return
+    if args.mode == "backward":
+        g = backward(args, kmc, workloads)
+        print(json.dumps({"backward": g}), flush=True)
+        return
 
     p = plain(args, kmc, workloads)
     value = p["ticks"] / p["sec"]
@@ -197,7 +228,7 @@ def main():
             "ops_per_launch": ops / p["launches"],
         },
     }
-    if not args.no_extras:
+    if args.mode == "all":
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
         line["batched"] = {"value": b["ticks"] / b["sec"], "unit": "site-updates/s",

@@ -1,12 +1,13 @@
 """Tile autotuner for batched runs.
 
-For every lattice side L of a workload the tuner times short persistent runs
-of a probe batch with each valid domain side B (B % 4 == 0, L/B even,
-B <= max_tile) and keeps the fastest in site-updates/s.  The choice changes
-the dynamics (the paper's T_PAR depends on the partition) but not the
-equilibrium, which Eq. (general reversibility condition) guarantees for any
-partition; the chosen tile is written into the descriptors, so every run
-(and its oracle replay) uses the same partition.  Choices persist as JSON.
+The domain side B of every lattice side L in a batch is chosen by timing
+the real batch: coordinate descent over L, trying each valid B (B % 4 == 0,
+L/B even, B <= max_tile) with the other sides fixed, keeping the fastest in
+site-updates/s of the persistent kernel.  The choice changes the dynamics
+(the paper's T_PAR depends on the partition) but not the equilibrium, which
+Eq. (general reversibility condition) guarantees for any partition; the
+chosen tile is written into the descriptors, so every run and its oracle
+replay use the same partition.  Choices persist as JSON keyed by workload.
 """
 import json
 import os
@@ -22,39 +23,54 @@ def valid_tiles(L, max_tile=32, min_tile=8):
             if L % B == 0 and (L // B) % 2 == 0]
 
 
-def tune(Ls, T=2.5, h=0.0, probe_replicas=512, sweeps=20, max_tile=32, seed=1234,
-         path=DEFAULT_PATH, steps_per_visit=0):
-    """Returns {L: best tile} and writes it to `path` (merged with what is
-    there).  Timing uses the persistent batched kernel on the GPU."""
+def _rate(descs, seed, sweeps):
     import torch
-    table = load(path)
     stream = torch.cuda.current_stream()
-    for L in sorted(set(int(x) for x in Ls)):
-        best, best_rate = None, -1.0
-        timings = {}
-        for B in valid_tiles(L, max_tile):
-            descs = [dict(L=L, tile=B, T=T, h=h, steps_per_visit=steps_per_visit)] * \
-                probe_replicas
-            lat = kmc.Lattice(descs, seed)
-            lat.run(2, 2, kmc.F_PERSISTENT)
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
-            b.record(stream)
-            torch.cuda.synchronize()
-            sec = a.elapsed_time(b) / 1e3
-            lat.close()
-            rate = probe_replicas * sweeps * L * L / sec
-            timings[B] = rate
-            if rate > best_rate:
-                best, best_rate = B, rate
-        table[str(L)] = {"tile": best, "site_updates_per_s": timings,
-                         "probe": dict(T=T, h=h, replicas=probe_replicas, sweeps=sweeps),
-                         "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    lat = kmc.Lattice(descs, seed)
+    lat.run(1, 1, kmc.F_PERSISTENT)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3
+    lat.close()
+    return sweeps * sum(d["L"] ** 2 for d in descs) / sec
+
+
+def tune_batch(name, descs, seed, sweeps=8, max_tile=32, passes=1, path=DEFAULT_PATH,
+               verbose=False):
+    """Chooses a tile per lattice side for the batch `descs` (dicts with L,
+    tile, ...), records the choice under `name` and returns {L: tile}."""
+    Ls = sorted({int(d["L"]) for d in descs})
+    tiles = {L: int(next(d["tile"] for d in descs if d["L"] == L)) for L in Ls}
+    with_tiles = lambda tl: [dict(d, tile=tl[int(d["L"])]) for d in descs]
+    best = _rate(with_tiles(tiles), seed, sweeps)
+    trials = [{"tiles": dict(tiles), "site_updates_per_s": best}]
+    for _ in range(passes):
+        for L in Ls:
+            for B in valid_tiles(L, max_tile):
+                if B == tiles[L]:
+                    continue
+                cand = dict(tiles)
+                cand[L] = B
+                r = _rate(with_tiles(cand), seed, sweeps)
+                trials.append({"tiles": dict(cand), "site_updates_per_s": r})
+                if verbose:
+                    print(f"[autotune] {name} L={L} B={B}: {r:.3e} site-updates/s", flush=True)
+                if r > best:
+                    best, tiles = r, cand
+    table = load(path)
+    table[name] = {"tiles": {str(k): v for k, v in tiles.items()},
+                   "site_updates_per_s": best, "sweeps": sweeps,
+                   "trials": [{"tiles": {str(k): v for k, v in t["tiles"].items()},
+                               "site_updates_per_s": t["site_updates_per_s"]}
+                              for t in trials],
+                   "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
     save(table, path)
-    return {int(k): v["tile"] for k, v in table.items()}
+    return tiles
 
 
 def load(path=DEFAULT_PATH):
@@ -71,16 +87,37 @@ def save(table, path=DEFAULT_PATH):
     os.replace(tmp, path)
 
 
-def tiles_for(Ls, path=DEFAULT_PATH, fallback=None):
-    """Tuned tile per L, falling back to `fallback` (or the largest valid
-    tile <= 32) for sides that were never tuned."""
-    table = load(path)
-    out = {}
-    for L in set(int(x) for x in Ls):
-        if str(L) in table:
-            out[L] = int(table[str(L)]["tile"])
-        elif fallback and L in fallback:
-            out[L] = fallback[L]
-        else:
-            out[L] = max(valid_tiles(L, 32, 4))
-    return out
+def tiles_for(name, path=DEFAULT_PATH):
+    """The tuned {L: tile} of workload `name`, or None."""
+    entry = load(path).get(name)
+    if not entry:
+        return None
+    return {int(k): int(v) for k, v in entry["tiles"].items()}
+
+
+def main():
+    """Tunes the two batched benchmark workloads on the current GPU and
+    writes the table to --out (default: next to this file)."""
+    import argparse
+
+    import torch
+
+    from . import workloads
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--sweeps", type=int, default=8)
+    args = ap.parse_args()
+    torch.cuda.set_stream(torch.cuda.Stream())
+    kmc.use_torch_allocator()
+    DEF = workloads.DEFAULT_TILE
+    seed, descs, _ = workloads.batched_4096(tiles=DEF)
+    print("batched_4096", tune_batch("batched_4096", descs, seed, sweeps=args.sweeps,
+                                     path=args.out, verbose=True), flush=True)
+    seed, descs, _ = workloads.differentiable_1024(tile=32)
+    print("differentiable_1024", tune_batch("differentiable_1024", descs, seed,
+                                            sweeps=args.sweeps, path=args.out,
+                                            verbose=True), flush=True)
+
+
+if __name__ == "__main__":
+    main()

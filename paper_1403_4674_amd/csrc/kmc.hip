@@ -437,6 +437,17 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         // persistent queues: per row-mask width, replicas with at least four
         // domains per colour and a large sweep run as a workgroup team, the
         // rest on single wavefronts; each list costliest first
+        // (with fewer replicas than 4 wavefronts per SIMD, every replica that
+        // can be split is split, so that the launch fills the chip)
+        int n_simd = 1024;
+        {
+            int dev = 0;
+            hipDeviceProp_t prop;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+                n_simd = 4 * prop.multiProcessorCount;
+        }
+        const bool few = n_rep < 4 * n_simd;
         std::vector<int32_t> order;
         for (int pass = 0; pass < 2; ++pass) {
             std::vector<int32_t> team, solo;
@@ -444,7 +455,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 const Rep &rp = c->reps[rho];
                 if ((rp.B > 32) != (pass == 1)) continue;
                 const int64_t ticks = (int64_t)rp.NI * rp.ND * rp.visits;
-                ((rp.ND / 4 >= 4 && ticks >= 8192) ? team : solo).push_back(rho);
+                const bool split = rp.ND / 4 >= 4 && (ticks >= 8192 || few);
+                (split ? team : solo).push_back(rho);
             }
             auto by_cost = [&](int a, int b) {
                 return sweep_cost(c->reps[a], c->desc[a]) > sweep_cost(c->reps[b], c->desc[b]);

@@ -8,6 +8,9 @@ The paper studies periodic square Ising lattices at 1/(beta J) = 2.4 with
 checkerboard or stripe domains (Sec. 3.2, Table 1); the five workloads below
 extend that shape to GPU sizes.
 """
+import json
+import os
+
 import numpy as np
 
 METROPOLIS = 0
@@ -41,6 +44,19 @@ def quench_4096():
     return 3, [desc], dict(sweeps=2000, record_every=10)
 
 
+TUNED_TILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
+
+
+def _tuned(name):
+    """Tile per lattice side chosen for workload `name` by the autotuner
+    (a JSON table next to this file), or None."""
+    if not os.path.exists(TUNED_TILES):
+        return None
+    with open(TUNED_TILES) as f:
+        entry = json.load(f).get(name)
+    return {int(k): int(v) for k, v in entry["tiles"].items()} if entry else None
+
+
 def batched_4096(n=4096, tiles=None, seed=4):
     """n replicas, L uniform in {16,24,32,48,64,128}, T ~ U[1.5, 3.5],
     h ~ U[-0.5, 0.5] from numpy default_rng(4); N_I = tile^2; 5000 sweeps."""
@@ -48,16 +64,18 @@ def batched_4096(n=4096, tiles=None, seed=4):
     Ls = rng.choice([16, 24, 32, 48, 64, 128], size=n)
     Ts = rng.uniform(1.5, 3.5, size=n)
     hs = rng.uniform(-0.5, 0.5, size=n)
-    tiles = tiles or DEFAULT_TILE
+    tiles = tiles or _tuned("batched_4096") or DEFAULT_TILE
     descs = [dict(L=int(L), tile=int(tiles[int(L)]), J=1.0, h=float(h), T=float(T),
                   steps_per_visit=0, rate_model=METROPOLIS)
              for L, T, h in zip(Ls, Ts, hs)]
     return 4, descs, dict(sweeps=5000, record_every=100)
 
 
-def differentiable_1024(n=1024, tile=32, seed=5):
+def differentiable_1024(n=1024, tile=None, seed=5):
     """n replicas of 64x64, T=2.5, J=1, h ~ U[-0.2, 0.2] from default_rng(5),
-    N_I = tile^2, 20000 sweeps, score on."""
+    N_I = tile^2 (tile tuned, else 32), 20000 sweeps, score on."""
+    if tile is None:
+        tile = (_tuned("differentiable_1024") or {64: 32})[64]
     rng = np.random.default_rng(seed)
     hs = rng.uniform(-0.2, 0.2, size=n)
     descs = [dict(L=64, tile=int(tile), J=1.0, h=float(h), T=2.5, steps_per_visit=0,
