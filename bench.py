@@ -64,14 +64,18 @@ def plain(args, kmc, workloads):
                 desc=d, seed=seed)
 
 
+def parse_tiles(text):
+    return {int(a): int(b) for a, b in (kv.split(":") for kv in text.split(","))} if text else None
+
+
 def batched(args, kmc, workloads):
     import torch
-    seed, descs, _ = workloads.batched_4096()
+    seed, descs, _ = workloads.batched_4096(tiles=parse_tiles(args.tiles))
     lat = kmc.Lattice(descs, seed)
     stream = torch.cuda.current_stream()
-    lat.run(2, 1, kmc.F_PERSISTENT)
+    lat.run(2, 1, kmc.F_PERSISTENT | args.flags)
     sec = timed(lambda: lat.run(args.batched_sweeps, args.batched_sweeps,
-                                kmc.F_PERSISTENT), stream)
+                                kmc.F_PERSISTENT | args.flags), stream)
     ticks = args.batched_sweeps * sum(x["L"] ** 2 for x in descs)
     lat.close()
     return dict(sec=sec, ticks=ticks, replicas=len(descs), sweeps=args.batched_sweeps)
@@ -161,6 +165,8 @@ def main():
                     choices=["all", "plain", "batched", "backward", "copy"],
                     help="all: the full line; the others run one part (for profiling)")
     ap.add_argument("--no-extras", action="store_true", help="same as --mode plain")
+    ap.add_argument("--tiles", default="", help="batched workload tiles, e.g. 16:8,24:12")
+    ap.add_argument("--flags", type=int, default=0, help="extra kmc_run_schedule flags (batched)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method's replicas and domains are "

@@ -63,6 +63,12 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
                                   replica and runs all of its sweeps          */
 #define KMC_F_GRAPH 0x4u       /* phase-by-phase path replayed from a captured
                                   hipGraph                                     */
+#define KMC_F_NO_MULTI 0x8u    /* with KMC_F_PERSISTENT: never run four domain
+                                  processes per wavefront                      */
+#define KMC_F_MULTI 0x20u      /* with KMC_F_PERSISTENT: run replicas with
+                                  domains of at most 16x16 four domain
+                                  processes per wavefront even in small batches
+                                  (default: only when the batch is large)      */
 /* flags of kmc_backward_score and kmc_observables */
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
@@ -139,6 +145,8 @@ kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
  * Errors: KMC_EINVAL (n_sweeps < 0, record_every < 1), KMC_ENOMEM, KMC_EDEVICE. */
 kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t record_every,
                             uint32_t flags);
+/* All execution forms give bit-identical results; KMC_F_MULTI and
+ * KMC_F_NO_MULTI only change how the work is laid out on the GPU. */
 
 /* Copies all records so far: out[rep * capacity + k] for replica rep and
  * record k < min(capacity, *n_rec_out).  *n_rec_out receives the number of

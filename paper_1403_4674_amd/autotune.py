@@ -41,14 +41,31 @@ def _rate(descs, seed, sweeps):
 
 
 def tune_batch(name, descs, seed, sweeps=8, max_tile=32, passes=1, path=DEFAULT_PATH,
-               verbose=False):
+               verbose=False, starts=None):
     """Chooses a tile per lattice side for the batch `descs` (dicts with L,
-    tile, ...), records the choice under `name` and returns {L: tile}."""
+    tile, ...), records the choice under `name` and returns {L: tile}.
+
+    Coordinate descent from the best of several starting points: the
+    descriptors' tiles, the largest valid tiles up to 16 (the range of the
+    four-domains-per-wavefront kernel, which only pays once most replicas
+    use it, so single-coordinate moves from large tiles never reach it), and
+    any `starts` given."""
     Ls = sorted({int(d["L"]) for d in descs})
-    tiles = {L: int(next(d["tile"] for d in descs if d["L"] == L)) for L in Ls}
     with_tiles = lambda tl: [dict(d, tile=tl[int(d["L"])]) for d in descs]
-    best = _rate(with_tiles(tiles), seed, sweeps)
-    trials = [{"tiles": dict(tiles), "site_updates_per_s": best}]
+    cands = [{L: int(next(d["tile"] for d in descs if d["L"] == L)) for L in Ls}]
+    small = {L: max(valid_tiles(L, 16, 4)) for L in Ls}
+    if small not in cands:
+        cands.append(small)
+    cands += [dict(s) for s in (starts or []) if s not in cands]
+    trials = []
+    best, tiles = -1.0, None
+    for c in cands:
+        r = _rate(with_tiles(c), seed, sweeps)
+        trials.append({"tiles": dict(c), "site_updates_per_s": r})
+        if verbose:
+            print(f"[autotune] {name} start {c}: {r:.3e} site-updates/s", flush=True)
+        if r > best:
+            best, tiles = r, dict(c)
     for _ in range(passes):
         for L in Ls:
             for B in valid_tiles(L, max_tile):

@@ -15,8 +15,10 @@
 
 #include "kmc.h"
 #include "kmc_device.h"
+#include "kmc_multi.h"
 
 using kmcdev::Ctl;
+using kmcdev::MItem;
 using kmcdev::Dom;
 using kmcdev::KParams;
 using kmcdev::Rates;
@@ -59,6 +61,14 @@ struct kmc_ctx {
     int32_t n_tasks = 0, n_tasks32 = 0;
     // persistent queues per row-mask width: [team..., solo...]
     int32_t n_team[2] = {0, 0}, n_solo[2] = {0, 0};
+    // multi-slot items (domains <= 16x16): [workgroup items..., wavefront items...]
+    std::vector<MItem> m_items;
+    int32_t n_m_wg = 0, n_m_wave = 0;
+    MItem *d_items = nullptr;
+    // the same replicas without the multi-slot form (KMC_F_NO_MULTI)
+    int32_t nm_team[2] = {0, 0}, nm_solo[2] = {0, 0};
+    int32_t *d_order_nm = nullptr;
+    bool multi_auto = false;  // the multi-slot items keep >= 2 wavefronts per SIMD
     int n_phase = 4;
 
     Rep *d_reps = nullptr;
@@ -262,21 +272,26 @@ void launch_sweep(kmc_ctx *c, KParams K) {
 }
 
 template <bool SCORE>
-void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps) {
+void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps,
+                       uint32_t flags) {
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
     const int waves = kmcdev::kWavesPerPersistentGroup;
+    const bool multi = !(flags & KMC_F_NO_MULTI) && (c->n_m_wg + c->n_m_wave) > 0 &&
+                       ((flags & KMC_F_MULTI) || c->multi_auto);
+    const int32_t *order = multi ? c->d_order : c->d_order_nm;
+    const int32_t *nt = multi ? c->n_team : c->nm_team;
+    const int32_t *ns = multi ? c->n_solo : c->nm_solo;
     int32_t off = 0;
     for (int g = 0; g < 2; ++g) {
-        const int nt = c->n_team[g], ns = c->n_solo[g];
-        if (!nt && !ns) continue;
-        K.order = c->d_order + off;
-        K.n_team = nt;
-        K.n_solo = ns;
-        off += nt + ns;
-        const int groups = std::max(1, std::min(nt + (ns + waves - 1) / waves, cus * 8));
+        if (!nt[g] && !ns[g]) continue;
+        K.order = order + off;
+        K.n_team = nt[g];
+        K.n_solo = ns[g];
+        off += nt[g] + ns[g];
+        const int groups = std::max(1, std::min(nt[g] + (ns[g] + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         if (g == 0)
             hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
@@ -286,6 +301,14 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps) 
             hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
                                dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
                                n_sweeps);
+    }
+    if (multi) {
+        const int groups = std::max(
+            1, std::min(c->n_m_wg + (c->n_m_wave + waves - 1) / waves, cus * 8));
+        hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
+        hipLaunchKernelGGL((kmcdev::k_persistent_multi<SCORE>), dim3(groups), dim3(64 * waves),
+                           0, c->stream, K, c->d_items, c->n_m_wg, c->n_m_wave, sweep0,
+                           (int64_t)0, n_sweeps);
     }
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "persistent launch");
@@ -345,7 +368,7 @@ void destroy_buffers(kmc_ctx *c) {
     void *bufs[] = {c->d_reps,  c->d_rates, c->d_spins, c->d_dom,   c->d_acc,
                     c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
                     c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
-                    c->r_ctl,   c->d_bins,  c->d_tmp_rec};
+                    c->r_ctl,   c->d_bins,  c->d_tmp_rec, c->d_order_nm, c->d_items};
     for (void *p : bufs) dev_free(c, p);
 }
 
@@ -434,11 +457,15 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();
             }
         c->n_tasks = (int32_t)task_rep.size();
-        // persistent queues: per row-mask width, replicas with at least four
-        // domains per colour and a large sweep run as a workgroup team, the
-        // rest on single wavefronts; each list costliest first
-        // (with fewer replicas than 4 wavefronts per SIMD, every replica that
-        // can be split is split, so that the launch fills the chip)
+        // persistent queues.  Replicas with domains of at most 16x16 may run
+        // in the multi-slot kernel (four domain processes per wavefront):
+        // one replica split over the slots of a workgroup (>= 16 domains per
+        // colour) or of a wavefront (>= 4), or four replicas of one shape per
+        // wavefront.  It is used when its items keep at least two wavefronts
+        // per SIMD busy.  The others, and every replica when the multi-slot
+        // form is not used, go to the one-domain-per-wavefront kernel: a
+        // workgroup team when the replica has >= 4 domains per colour and a
+        // large sweep (or the batch is small), else one wavefront.
         int n_simd = 1024;
         {
             int dev = 0;
@@ -448,26 +475,76 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 n_simd = 4 * prop.multiProcessorCount;
         }
         const bool few = n_rep < 4 * n_simd;
-        std::vector<int32_t> order;
-        for (int pass = 0; pass < 2; ++pass) {
-            std::vector<int32_t> team, solo;
-            for (int rho = 0; rho < n_rep; ++rho) {
-                const Rep &rp = c->reps[rho];
-                if ((rp.B > 32) != (pass == 1)) continue;
-                const int64_t ticks = (int64_t)rp.NI * rp.ND * rp.visits;
-                const bool split = rp.ND / 4 >= 4 && (ticks >= 8192 || few);
-                (split ? team : solo).push_back(rho);
-            }
-            auto by_cost = [&](int a, int b) {
-                return sweep_cost(c->reps[a], c->desc[a]) > sweep_cost(c->reps[b], c->desc[b]);
+        auto by_cost = [&](int a, int b) {
+            return sweep_cost(c->reps[a], c->desc[a]) > sweep_cost(c->reps[b], c->desc[b]);
+        };
+        std::vector<int32_t> mrep;  // multi-slot candidates
+        for (int rho = 0; rho < n_rep; ++rho)
+            if (c->reps[rho].B <= 16) mrep.push_back(rho);
+        {
+            std::stable_sort(mrep.begin(), mrep.end(), by_cost);
+            std::vector<MItem> wg, wv;
+            std::vector<std::vector<int32_t>> pending;  // inter groups by shape
+            auto same_shape = [&](int a, int b) {
+                const Rep &x = c->reps[a], &y = c->reps[b];
+                return x.L == y.L && x.B == y.B && x.NI == y.NI && x.sched == y.sched;
             };
-            std::stable_sort(team.begin(), team.end(), by_cost);
-            std::stable_sort(solo.begin(), solo.end(), by_cost);
-            c->n_team[pass] = (int32_t)team.size();
-            c->n_solo[pass] = (int32_t)solo.size();
-            order.insert(order.end(), team.begin(), team.end());
-            order.insert(order.end(), solo.begin(), solo.end());
+            for (int rho : mrep) {
+                const int per_colour = c->reps[rho].ND / 4;
+                if (per_colour >= 4) {
+                    MItem it{1, per_colour >= 16 ? 4 : 1, {rho, -1, -1, -1}};
+                    (it.nw == 4 ? wg : wv).push_back(it);
+                    continue;
+                }
+                bool placed = false;
+                for (auto &grp : pending)
+                    if (grp.size() < 4 && same_shape(grp[0], rho)) {
+                        grp.push_back(rho);
+                        placed = true;
+                        if (grp.size() == 4) {
+                            wv.push_back(MItem{0, 1, {grp[0], grp[1], grp[2], grp[3]}});
+                            grp.clear();
+                        }
+                        break;
+                    }
+                if (!placed) pending.push_back({rho});
+            }
+            for (auto &grp : pending)
+                if (!grp.empty()) {
+                    MItem it{0, 1, {-1, -1, -1, -1}};
+                    for (size_t q = 0; q < grp.size(); ++q) it.rho[q] = grp[q];
+                    wv.push_back(it);
+                }
+            const int64_t m_waves = 4 * (int64_t)wg.size() + (int64_t)wv.size();
+            c->m_items = wg;
+            c->m_items.insert(c->m_items.end(), wv.begin(), wv.end());
+            c->n_m_wg = (int32_t)wg.size();
+            c->n_m_wave = (int32_t)wv.size();
+            c->multi_auto = !mrep.empty() && m_waves >= 2 * n_simd;
         }
+        auto build_queue = [&](bool use_multi, int32_t *n_team, int32_t *n_solo) {
+            std::vector<int32_t> order;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<int32_t> team, solo;
+                for (int rho = 0; rho < n_rep; ++rho) {
+                    const Rep &rp = c->reps[rho];
+                    if ((rp.B > 32) != (pass == 1)) continue;
+                    if (use_multi && rp.B <= 16) continue;
+                    const int64_t ticks = (int64_t)rp.NI * rp.ND * rp.visits;
+                    const bool split = rp.ND / 4 >= 4 && (ticks >= 8192 || few);
+                    (split ? team : solo).push_back(rho);
+                }
+                std::stable_sort(team.begin(), team.end(), by_cost);
+                std::stable_sort(solo.begin(), solo.end(), by_cost);
+                n_team[pass] = (int32_t)team.size();
+                n_solo[pass] = (int32_t)solo.size();
+                order.insert(order.end(), team.begin(), team.end());
+                order.insert(order.end(), solo.begin(), solo.end());
+            }
+            return order;
+        };
+        std::vector<int32_t> order = build_queue(!c->m_items.empty(), c->n_team, c->n_solo);
+        std::vector<int32_t> order_nm = build_queue(false, c->nm_team, c->nm_solo);
 
         c->d_reps = alloc_n<Rep>(c, n_rep);
         c->d_rates = alloc_n<Rates>(c, n_rep);
@@ -477,6 +554,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         c->d_ctl = alloc_n<Ctl>(c, 1);
         c->d_task_rep = alloc_n<int32_t>(c, c->n_tasks);
         c->d_order = alloc_n<int32_t>(c, n_rep);
+        c->d_order_nm = alloc_n<int32_t>(c, n_rep);
+        c->d_items = alloc_n<MItem>(c, (int64_t)c->m_items.size());
         hipStream_t s = c->stream;
         hip_check(c, hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Rep) * n_rep,
                                     hipMemcpyHostToDevice, s), "copy reps");
@@ -485,8 +564,14 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         hip_check(c, hipMemcpyAsync(c->d_task_rep, task_rep.data(),
                                     sizeof(int32_t) * std::max<size_t>(task_rep.size(), 1),
                                     hipMemcpyHostToDevice, s), "copy tasks");
-        hip_check(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * n_rep,
+        hip_check(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * order.size(),
                                     hipMemcpyHostToDevice, s), "copy order");
+        hip_check(c, hipMemcpyAsync(c->d_order_nm, order_nm.data(), sizeof(int32_t) * n_rep,
+                                    hipMemcpyHostToDevice, s), "copy order");
+        if (!c->m_items.empty())
+            hip_check(c, hipMemcpyAsync(c->d_items, c->m_items.data(),
+                                        sizeof(MItem) * c->m_items.size(),
+                                        hipMemcpyHostToDevice, s), "copy items");
         hip_check(c, hipMemsetAsync(c->d_dom, 0, sizeof(Dom) * std::max(dom, 1), s), "zero");
         hip_check(c, hipMemsetAsync(c->d_acc, 0, sizeof(RepAcc) * n_rep, s), "zero");
         hip_check(c, hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s), "zero");
@@ -564,7 +649,7 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, c->stream, c->d_ctl,
                            (int64_t)0, c->n_rec, (int64_t)record_every, c->sweep);
         if (flags & KMC_F_PERSISTENT)
-            launch_persistent<false>(c, K, c->sweep, n_sweeps);
+            launch_persistent<false>(c, K, c->sweep, n_sweeps, flags);
         else if (flags & KMC_F_GRAPH)
             run_graph(c, n_sweeps);
         else
@@ -649,7 +734,7 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
         if (c->ck_flags & KMC_F_PERSISTENT)
-            launch_persistent<true>(c, K, c->ck_sweep, c->ck_n_sweeps);
+            launch_persistent<true>(c, K, c->ck_sweep, c->ck_n_sweeps, c->ck_flags);
         else
             for (int64_t i = 0; i < c->ck_n_sweeps; ++i) launch_sweep<true>(c, K);
         const hipMemcpyKind kind =

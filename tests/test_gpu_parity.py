@@ -134,3 +134,39 @@ def test_resume_and_determinism(torch_cuda, oracle_lib):
     rb = b.records()
     for f in ("M", "B", "events"):
         assert np.array_equal(rb[f], g[f])
+
+
+MULTI_MIX = (
+    # four-replica groups (one domain per colour), a partial group
+    [dict(L=16, tile=8, T=2.3 + 0.1 * i, h=0.05 * i) for i in range(6)]
+    + [dict(L=24, tile=12, T=2.0 + 0.2 * i, h=-0.1) for i in range(5)]
+    + [dict(L=32, tile=16, T=3.0, h=0.2, rate_model=kmc.RATE_BARKER) for _ in range(3)]
+    # one replica split over the slots of a wavefront (4 and 9 per colour)
+    + [dict(L=32, tile=8, T=2.6, h=0.0), dict(L=48, tile=8, T=1.8, h=0.3),
+       dict(L=64, tile=16, T=2.4, h=-0.2, schedule=kmc.SCHED_PALINDROME)]
+    # over the slots of a workgroup (16 per colour)
+    + [dict(L=128, tile=16, T=2.269, h=0.0), dict(L=64, tile=8, T=3.3, h=0.1)]
+)
+
+
+def test_multi_slot_form_is_bit_identical(torch_cuda, oracle_lib):
+    descs = MULTI_MIX
+    say(f"multi-slot form, {len(descs)} replicas")
+    a = kmc.Lattice(descs, 123)
+    b = kmc.Lattice(descs, 123)
+    a.run(9, 3, kmc.F_PERSISTENT | kmc.F_NO_MULTI)
+    b.run(9, 3, kmc.F_PERSISTENT | kmc.F_MULTI)
+    ra, rb = a.records(), b.records()
+    for f in ("sweep", "M", "B", "events", "steps"):
+        assert np.array_equal(ra[f], rb[f]), f
+    np.testing.assert_allclose(ra["t"], rb["t"], rtol=1e-13)
+    for rho in range(len(descs)):
+        assert np.array_equal(a.spins(rho), b.spins(rho)), rho
+        sa, ca, ea = a.domain_state(rho)
+        sb, cb, eb = b.domain_state(rho)
+        assert np.array_equal(ea, eb)
+        np.testing.assert_allclose(sa + ca, sb + cb, rtol=1e-13)
+    for rho in (0, 6, 11, 14, 15, 16, 17, 18):
+        o = oracle_for(oracle_lib, descs[rho], 123, rho)
+        orec = o.run(9, 3)
+        assert_replica_equal(b, rho, o, rb[rho], orec, f"multi replica {rho}")

@@ -174,3 +174,20 @@ def test_fluctuation_identity_and_crn_differences(torch_cuda):
     fd = (Mp - Mm) / (2 * dh)
     z2 = zscore(fd - fi_h)
     assert abs(z2) < 4.5, (fd.mean(), fi_h.mean(), z2)
+
+
+def test_backward_score_multi_slot(torch_cuda, oracle_lib):
+    from tests.test_gpu_parity import MULTI_MIX
+    descs = MULTI_MIX
+    say("score replay, multi-slot form")
+    lat = kmc.Lattice(descs, 5)
+    lat.run(7, 2, kmc.F_PERSISTENT | kmc.F_MULTI | kmc.F_CHECKPOINT)
+    g = lat.score(4)
+    ref = kmc.Lattice(descs, 5)
+    ref.run(7, 2, kmc.F_PERSISTENT | kmc.F_NO_MULTI | kmc.F_CHECKPOINT)
+    r = ref.score(4)
+    np.testing.assert_allclose(g, r, rtol=1e-10, atol=1e-7)
+    for rho in (0, 6, 15, 17):
+        o = oracle_for(oracle_lib, descs[rho], 5, rho)
+        _, sc = o.run(7, 2, score=True)
+        np.testing.assert_allclose(g[rho], sc, rtol=1e-10, atol=1e-7)
