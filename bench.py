@@ -91,9 +91,13 @@ def backward(args, kmc, workloads):
     fwd = timed(lambda: lat.run(n, 10, kmc.F_PERSISTENT | kmc.F_CHECKPOINT), stream)
     out = torch.empty((len(descs), n // 10, 2), dtype=torch.float64, device="cuda")
     bwd = timed(lambda: lat.score(n // 10, out), stream)
+    # the fused form: the forward accumulates the score as it runs
+    fused = timed(lambda: lat.run(n, 10, kmc.F_PERSISTENT | kmc.F_SCORE), stream)
+    fused_bwd = timed(lambda: lat.score(n // 10, out), stream)
     ticks = n * sum(x["L"] ** 2 for x in descs)
     lat.close()
     return dict(fwd=fwd, bwd=bwd, ticks=ticks, overhead=(fwd + bwd) / fwd - 1.0,
+                fused=fused + fused_bwd, fused_overhead=(fused + fused_bwd) / fwd - 1.0,
                 replicas=len(descs), sweeps=n)
 
 
@@ -244,7 +248,10 @@ def main():
                             "overhead": g["overhead"], "replicas": g["replicas"],
                             "sweeps": g["sweeps"],
                             "fwd_plus_bwd_vs_plain": (g["ticks"] / (g["fwd"] + g["bwd"]))
-                            / value}
+                            / value,
+                            "fused_overhead": g["fused_overhead"],
+                            "fused_site_updates_per_s": g["ticks"] / g["fused"],
+                            "fused_vs_plain": (g["ticks"] / g["fused"]) / value}
         line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

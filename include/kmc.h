@@ -61,14 +61,19 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
 #define KMC_F_CHECKPOINT 0x1u  /* save the start state for kmc_backward_score */
 #define KMC_F_PERSISTENT 0x2u  /* one persistent launch: one wavefront owns a
                                   replica and runs all of its sweeps          */
-#define KMC_F_GRAPH 0x4u       /* phase-by-phase path replayed from a captured
-                                  hipGraph                                     */
+#define KMC_F_GRAPH 0x4u       /* replay from a captured hipGraph: alone, G
+                                  phase-by-phase sweeps per graph; with
+                                  KMC_F_PERSISTENT, one persistent launch of
+                                  record_every sweeps per graph                */
 #define KMC_F_NO_MULTI 0x8u    /* with KMC_F_PERSISTENT: never run four domain
                                   processes per wavefront                      */
 #define KMC_F_MULTI 0x20u      /* with KMC_F_PERSISTENT: run replicas with
                                   domains of at most 16x16 four domain
                                   processes per wavefront even in small batches
                                   (default: only when the batch is large)      */
+#define KMC_F_SCORE 0x40u      /* accumulate the likelihood-ratio score of
+                                  every tick while the run proceeds (the
+                                  backward call then only copies it out)      */
 /* flags of kmc_backward_score and kmc_observables */
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
@@ -157,15 +162,18 @@ kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capacity,
                            int64_t *n_rec_out, uint32_t flags);
 
 /* Likelihood-ratio path score of the last kmc_run_schedule call made with
- * KMC_F_CHECKPOINT: replays that call from its saved start state with a
- * dedicated kernel and accumulates, for every tick, d ln P/d(J, h) of the
+ * KMC_F_CHECKPOINT or KMC_F_SCORE.  With KMC_F_SCORE the run accumulated the
+ * score itself and this call copies it out.  Otherwise the call replays the
+ * run from its saved start state with a dedicated kernel (bit-exact: every
+ * decision is integer) and accumulates, for every tick, d ln P/d(J, h) of the
  * tick chain (an event of class c adds d ln w_c/d theta; a null tick adds
  * d ln(1 - R_w/n_d)/d theta with R_w the domain's total FP64 rate).  Output
  * score[(rep * capacity + k) * 2 + {0: J, 1: h}] for interval k: the ticks of
  * sweeps (k*record_every, (k+1)*record_every] of that call; the number of
  * intervals is ceil(n_sweeps / record_every) and must be <= capacity.
  * The live state of the context is not changed.  KMC_ESTATE without a
- * checkpoint.  Host output synchronises; KMC_F_DEVICE_OUT enqueues only. */
+ * checkpoint or score.  Host output synchronises; KMC_F_DEVICE_OUT enqueues
+ * only. */
 kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capacity,
                               uint32_t flags);
 

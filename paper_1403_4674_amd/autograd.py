@@ -20,16 +20,21 @@ from . import kmc
 
 class KmcFunction(torch.autograd.Function):
     """obs = KmcFunction.apply(J, h, base_descs, seed, n_sweeps, record_every,
-    persistent).  J, h: float64 tensors [n_rep].  obs: float64 [n_rep, n_rec, 2]
-    with (m, e) = (M/N, E/N) per site, E = -J B - h M."""
+    persistent, fused).  J, h: float64 tensors [n_rep].  obs: float64
+    [n_rep, n_rec, 2] with (m, e) = (M/N, E/N) per site, E = -J B - h M.
+    fused=False (default): the forward saves its start state and backward
+    replays the run with the score kernel; fused=True: the forward also
+    accumulates the score and backward only reads it."""
 
     @staticmethod
-    def forward(ctx, J, h, base_descs, seed, n_sweeps, record_every, persistent=True):
+    def forward(ctx, J, h, base_descs, seed, n_sweeps, record_every, persistent=True,
+                fused=False):
         Jh = J.detach().double().cpu().numpy()
         hh = h.detach().double().cpu().numpy()
         descs = [dict(d, J=float(a), h=float(b)) for d, a, b in zip(base_descs, Jh, hh)]
         lat = kmc.Lattice(descs, seed)
-        flags = kmc.F_CHECKPOINT | (kmc.F_PERSISTENT if persistent else 0)
+        flags = (kmc.F_SCORE if fused else kmc.F_CHECKPOINT) | \
+            (kmc.F_PERSISTENT if persistent else 0)
         lat.run(n_sweeps, record_every, flags)
         rec = lat.records()
         N = np.array([d["L"] ** 2 for d in descs], dtype=np.float64)[:, None]
@@ -67,7 +72,7 @@ class KmcFunction(torch.autograd.Function):
         gJ = lr[:, 0] - (grad_obs[..., 1] * b_site).sum(1)
         gh = lr[:, 1] - (grad_obs[..., 1] * m_site).sum(1)
         ctx.lat.close()
-        return gJ, gh, None, None, None, None, None
+        return gJ, gh, None, None, None, None, None, None
 
 
 def windowed_lr_derivative(O, bins, window, n_center):

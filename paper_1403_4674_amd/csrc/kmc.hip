@@ -91,6 +91,9 @@ struct kmc_ctx {
     int64_t ck_sweep = 0, ck_n_sweeps = 0;
     int32_t ck_rec_every = 1;
     uint32_t ck_flags = 0;
+    // the score of the last run with KMC_F_SCORE, accumulated while it ran
+    bool fused_score = false;
+    int64_t fused_bins = 0;
 
     // replay buffers of kmc_backward_score
     int8_t *r_spins = nullptr;
@@ -102,9 +105,12 @@ struct kmc_ctx {
     Record *d_tmp_rec = nullptr;
     int64_t tmp_rec_cap = 0;
 
-    // captured phase-by-phase sweeps
+    // captured phase-by-phase sweeps, and captured persistent chunks
     hipGraphExec_t graph = nullptr;
     int graph_sweeps = 0;
+    hipGraphExec_t pgraph = nullptr;
+    int64_t pgraph_chunk = 0;
+    uint32_t pgraph_key = 0;
 
     std::string err;
 };
@@ -272,8 +278,7 @@ void launch_sweep(kmc_ctx *c, KParams K) {
 }
 
 template <bool SCORE>
-void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps,
-                       uint32_t flags) {
+void launch_persistent(kmc_ctx *c, KParams K, int64_t n_sweeps, uint32_t flags) {
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -295,20 +300,17 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t sweep0, int64_t n_sweeps,
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         if (g == 0)
             hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
-                               dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
-                               n_sweeps);
+                               dim3(64 * waves), 0, c->stream, K, n_sweeps);
         else
             hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
-                               dim3(64 * waves), 0, c->stream, K, sweep0, (int64_t)0,
-                               n_sweeps);
+                               dim3(64 * waves), 0, c->stream, K, n_sweeps);
     }
     if (multi) {
         const int groups = std::max(
             1, std::min(c->n_m_wg + (c->n_m_wave + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         hipLaunchKernelGGL((kmcdev::k_persistent_multi<SCORE>), dim3(groups), dim3(64 * waves),
-                           0, c->stream, K, c->d_items, c->n_m_wg, c->n_m_wave, sweep0,
-                           (int64_t)0, n_sweeps);
+                           0, c->stream, K, c->d_items, c->n_m_wg, c->n_m_wave, n_sweeps);
     }
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "persistent launch");
@@ -326,10 +328,23 @@ void ensure_records(kmc_ctx *c, int64_t need) {
     dev_free(c, c->d_rec);
     c->d_rec = p;
     c->rec_cap = cap;
-    if (c->graph) {  // the captured graph holds the old record pointer
+    if (c->graph) {  // the captured graphs hold the old record pointer
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
     }
+    if (c->pgraph) {
+        (void)hipGraphExecDestroy(c->pgraph);
+        c->pgraph = nullptr;
+    }
+}
+
+void ensure_bins(kmc_ctx *c, int64_t n_bins) {
+    if (n_bins <= c->bins_cap) return;
+    hip_check(c, hipStreamSynchronize(c->stream), "bins sync");
+    dev_free(c, c->d_bins);
+    c->d_bins = nullptr;
+    c->d_bins = alloc_n<double>(c, n_bins * c->n_rep * 2);
+    c->bins_cap = n_bins;
 }
 
 void run_graph(kmc_ctx *c, int64_t n_sweeps) {
@@ -360,11 +375,48 @@ void run_graph(kmc_ctx *c, int64_t n_sweeps) {
     for (; i < n_sweeps; ++i) launch_sweep<false>(c, params(c));
 }
 
+// Persistent form replayed from a captured graph: one graph holds one
+// chunk (queue reset, persistent launch(es) of `chunk` sweeps, counter
+// advance); the kernels read the sweep counters from device memory, so
+// every replay continues where the previous one stopped.
+void run_persistent_graph(kmc_ctx *c, KParams K, int64_t n_sweeps, int32_t record_every,
+                          uint32_t flags) {
+    const int64_t chunk = std::min<int64_t>(record_every, n_sweeps);
+    const uint32_t key = flags & (KMC_F_MULTI | KMC_F_NO_MULTI);
+    if (!c->pgraph || c->pgraph_chunk != chunk || c->pgraph_key != key) {
+        if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
+        c->pgraph = nullptr;
+        if (!c->stream && !c->graph_stream)
+            hip_check(c, hipStreamCreate(&c->graph_stream), "stream create");
+        hipStream_t gs = c->stream ? c->stream : c->graph_stream;
+        hipStream_t saved = c->stream;
+        hipGraph_t g;
+        c->stream = gs;
+        hip_check(c, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal),
+                  "begin capture");
+        launch_persistent<false>(c, K, chunk, flags);
+        c->stream = saved;
+        hip_check(c, hipStreamEndCapture(gs, &g), "end capture");
+        hipError_t e = hipGraphInstantiate(&c->pgraph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(c, e, "graph instantiate");
+        c->pgraph_chunk = chunk;
+        c->pgraph_key = key;
+    }
+    hipStream_t gs = c->stream ? c->stream : c->graph_stream;
+    int64_t i = 0;
+    for (; i + chunk <= n_sweeps; i += chunk)
+        hip_check(c, hipGraphLaunch(c->pgraph, gs), "graph launch");
+    if (i < n_sweeps) launch_persistent<false>(c, K, n_sweeps - i, flags);
+}
+
 int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * d.L; }
 
 void destroy_buffers(kmc_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
+    if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
+    c->pgraph = nullptr;
     void *bufs[] = {c->d_reps,  c->d_rates, c->d_spins, c->d_dom,   c->d_acc,
                     c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
                     c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
@@ -623,8 +675,8 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             fail(c, KMC_EINVAL, "n_sweeps must be >= 0 and record_every >= 1");
         if (c->sweep + n_sweeps > 0xFFFFFFFFll)
             fail(c, KMC_EINVAL, "sweep counter would exceed 2^32 - 1");
-        if ((flags & KMC_F_PERSISTENT) && (flags & KMC_F_GRAPH))
-            fail(c, KMC_EINVAL, "KMC_F_PERSISTENT and KMC_F_GRAPH are exclusive");
+        if ((flags & KMC_F_SCORE) && (flags & KMC_F_GRAPH))
+            fail(c, KMC_EINVAL, "KMC_F_SCORE is not available with KMC_F_GRAPH");
         if (n_sweeps == 0) return KMC_OK;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
@@ -646,14 +698,40 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             c->ck_flags = flags;
         }
         KParams K = params(c);
+        const bool score = (flags & KMC_F_SCORE) != 0;
+        if (score || (flags & KMC_F_CHECKPOINT)) c->fused_score = false;
+        if (score) {
+            const int64_t n_bins = (n_sweeps + record_every - 1) / record_every;
+            ensure_bins(c, n_bins);
+            const int64_t nb = n_bins * c->n_rep * 2;
+            hipLaunchKernelGGL(kmcdev::k_fill_f64, dim3((unsigned)((nb + 255) / 256)),
+                               dim3(256), 0, c->stream, c->d_bins, nb, 0.0);
+            K.bins = c->d_bins;
+            K.n_bins = (int32_t)n_bins;
+        }
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, c->stream, c->d_ctl,
                            (int64_t)0, c->n_rec, (int64_t)record_every, c->sweep);
-        if (flags & KMC_F_PERSISTENT)
-            launch_persistent<false>(c, K, c->sweep, n_sweeps, flags);
-        else if (flags & KMC_F_GRAPH)
+        if (flags & KMC_F_PERSISTENT) {
+            if (score)
+                launch_persistent<true>(c, K, n_sweeps, flags);
+            else if (flags & KMC_F_GRAPH)
+                run_persistent_graph(c, K, n_sweeps, record_every, flags);
+            else
+                launch_persistent<false>(c, K, n_sweeps, flags);
+        } else if (flags & KMC_F_GRAPH) {
             run_graph(c, n_sweeps);
-        else
-            for (int64_t i = 0; i < n_sweeps; ++i) launch_sweep<false>(c, K);
+        } else {
+            for (int64_t i = 0; i < n_sweeps; ++i) {
+                if (score)
+                    launch_sweep<true>(c, K);
+                else
+                    launch_sweep<false>(c, K);
+            }
+        }
+        if (score) {
+            c->fused_score = true;
+            c->fused_bins = (n_sweeps + record_every - 1) / record_every;
+        }
         c->n_rec += n_sweeps / record_every;
         c->sweep += n_sweeps;
     } catch (const Fail &f) {
@@ -696,8 +774,23 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
                                          uint32_t flags) {
     if (!c) return KMC_EINVAL;
     try {
+        const hipMemcpyKind kind =
+            (flags & KMC_F_DEVICE_OUT) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (c->fused_score) {  // accumulated by the run itself
+            const int64_t n_bins = c->fused_bins;
+            if (!score || capacity < n_bins)
+                fail(c, KMC_EINVAL, "score buffer smaller than the number of intervals");
+            hip_check(c, hipMemcpy2DAsync(score, (size_t)capacity * 2 * sizeof(double),
+                                          c->d_bins, (size_t)n_bins * 2 * sizeof(double),
+                                          (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind,
+                                          c->stream),
+                      "score copy");
+            if (!(flags & KMC_F_DEVICE_OUT))
+                hip_check(c, hipStreamSynchronize(c->stream), "score sync");
+            return KMC_OK;
+        }
         if (!c->have_ckpt)
-            fail(c, KMC_ESTATE, "no run with KMC_F_CHECKPOINT to replay");
+            fail(c, KMC_ESTATE, "no run with KMC_F_CHECKPOINT or KMC_F_SCORE");
         const int64_t n_bins = (c->ck_n_sweeps + c->ck_rec_every - 1) / c->ck_rec_every;
         if (!score || capacity < n_bins)
             fail(c, KMC_EINVAL, "score buffer smaller than the number of intervals");
@@ -707,12 +800,7 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
             c->r_acc = alloc_n<RepAcc>(c, c->n_rep);
             c->r_ctl = alloc_n<Ctl>(c, 1);
         }
-        if (n_bins > c->bins_cap) {
-            dev_free(c, c->d_bins);
-            c->d_bins = nullptr;
-            c->d_bins = alloc_n<double>(c, n_bins * c->n_rep * 2);
-            c->bins_cap = n_bins;
-        }
+        ensure_bins(c, n_bins);
         hipStream_t s = c->stream;
         hip_check(c, hipMemcpyAsync(c->r_spins, c->c_spins, c->spin_bytes,
                                     hipMemcpyDeviceToDevice, s), "replay copy");
@@ -734,11 +822,9 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
         if (c->ck_flags & KMC_F_PERSISTENT)
-            launch_persistent<true>(c, K, c->ck_sweep, c->ck_n_sweeps, c->ck_flags);
+            launch_persistent<true>(c, K, c->ck_n_sweeps, c->ck_flags);
         else
             for (int64_t i = 0; i < c->ck_n_sweeps; ++i) launch_sweep<true>(c, K);
-        const hipMemcpyKind kind =
-            (flags & KMC_F_DEVICE_OUT) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         hip_check(c, hipMemcpy2DAsync(score, (size_t)capacity * 2 * sizeof(double), c->d_bins,
                                       (size_t)n_bins * 2 * sizeof(double),
                                       (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind, s),

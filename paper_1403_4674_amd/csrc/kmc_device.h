@@ -513,8 +513,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         const double Rh = rowsum16_f64(nl * ah_lane, lane);
         const double den = (double)nd - Rw;
         if (den > 0.0) {
-            out.sJ += (double)m * (-RJ / den);
-            out.sh += (double)m * (-Rh / den);
+            const double md = (double)m / den;
+            out.sJ -= md * RJ;
+            out.sh -= md * Rh;
         }
     };
 
@@ -878,9 +879,13 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
 // are drained.  One call site keeps the domain process inlined once.
 template <typename MT, bool SCORE>
 __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
-    KParams K, int64_t sweep0, int64_t run_done0, int64_t n_sweeps) {
+    KParams K, int64_t n_sweeps) {
     __shared__ __attribute__((aligned(16)))
     uint8_t lds_all[kWavesPerPersistentGroup][kLdsPerWave];
+    // the sweep counters come from device memory, so a captured launch can
+    // be replayed: k_advance moves them on after the launch
+    const int64_t sweep0 = K.ctl->sweep;
+    const int64_t run_done0 = K.ctl->run_done;
     __shared__ TeamShared ts;
     __shared__ int s_item;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));

@@ -192,8 +192,9 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
         const double Rh = sum_row_f64(nl * ah_lane, base);
         const double den = (double)nd - Rw;
         if (act && m && den > 0.0) {
-            out.sJ += (double)m * (-RJ / den);
-            out.sh += (double)m * (-Rh / den);
+            const double md = (double)m / den;
+            out.sJ -= md * RJ;
+            out.sh -= md * Rh;
         }
     };
 
@@ -516,11 +517,14 @@ __device__ void run_item(const KParams &K, const MItem &it, int wave, int lane, 
 
 // Multi-slot persistent kernel: workgroup items (teams of four wavefronts)
 // first, then wavefront items; every wavefront leaves once both queues are
-// drained.
+// drained.  The forward instantiation is held to 168 registers (three
+// wavefronts per SIMD, no spills); the score instantiation keeps two.
 template <bool SCORE>
-__global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent_multi(
+__global__ __launch_bounds__(64 * kWavesPerPersistentGroup) __attribute__((amdgpu_waves_per_eu(SCORE ? 2 : 3, 8))) void k_persistent_multi(
     KParams K, const MItem *__restrict__ items, int n_wg_items, int n_wave_items,
-    int64_t sweep0, int64_t run_done0, int64_t n_sweeps) {
+    int64_t n_sweeps) {
+    const int64_t sweep0 = K.ctl->sweep;  // device counters: replayable launch
+    const int64_t run_done0 = K.ctl->run_done;
     __shared__ __attribute__((aligned(16)))
     uint8_t lds_all[kWavesPerPersistentGroup][kSlots * kSlotLds];
     __shared__ MultiShared ms;

@@ -170,3 +170,29 @@ def test_multi_slot_form_is_bit_identical(torch_cuda, oracle_lib):
         o = oracle_for(oracle_lib, descs[rho], 123, rho)
         orec = o.run(9, 3)
         assert_replica_equal(b, rho, o, rb[rho], orec, f"multi replica {rho}")
+
+
+def test_persistent_graph_replays(torch_cuda, oracle_lib):
+    """Persistent chunks replayed from one captured graph, several runs with
+    reads of the results (synchronising host work) between the replays; every
+    replay is checked against eager launches."""
+    descs = MULTI_MIX[:6] + [dict(L=32, tile=16, T=2.2), dict(L=64, tile=32, T=2.8, h=0.1)]
+    say("persistent + graph, 3 runs x 4 replays")
+    a = kmc.Lattice(descs, 31)
+    b = kmc.Lattice(descs, 31)
+    for run in range(3):
+        a.run(8, 2, kmc.F_PERSISTENT)
+        b.run(8, 2, kmc.F_PERSISTENT | kmc.F_GRAPH)
+        ra, rb = a.records(), b.records()
+        assert ra.shape == rb.shape == (len(descs), 4 * (run + 1))
+        for f in ("sweep", "M", "B", "events", "steps"):
+            assert np.array_equal(ra[f], rb[f]), (run, f)
+        np.testing.assert_allclose(ra["t"], rb["t"], rtol=1e-13)
+        for rho in range(len(descs)):
+            assert np.array_equal(a.spins(rho), b.spins(rho)), (run, rho)
+    b.run(5, 2, kmc.F_PERSISTENT | kmc.F_GRAPH)  # two replays and a remainder
+    a.run(5, 2, kmc.F_PERSISTENT)
+    assert np.array_equal(a.records(), b.records())
+    o = oracle_for(oracle_lib, descs[6], 31, 6)
+    orec = o.run(29, 2)
+    assert_replica_equal(b, 6, o, b.records()[6], orec, "graph replica 6")

@@ -191,3 +191,24 @@ def test_backward_score_multi_slot(torch_cuda, oracle_lib):
         o = oracle_for(oracle_lib, descs[rho], 5, rho)
         _, sc = o.run(7, 2, score=True)
         np.testing.assert_allclose(g[rho], sc, rtol=1e-10, atol=1e-7)
+
+
+@pytest.mark.parametrize("flags", [kmc.F_PERSISTENT, kmc.F_PERSISTENT | kmc.F_MULTI, 0])
+def test_fused_score_equals_replay(torch_cuda, flags):
+    from tests.test_gpu_parity import MULTI_MIX
+    descs = MULTI_MIX[:8] + DESCS
+    say(f"fused score vs replay, flags {flags}")
+    a = kmc.Lattice(descs, 17)
+    b = kmc.Lattice(descs, 17)
+    a.run(6, 3, flags | kmc.F_CHECKPOINT)
+    b.run(6, 3, flags | kmc.F_SCORE)
+    ga, gb = a.score(2), b.score(2)
+    if flags & kmc.F_PERSISTENT:
+        assert np.array_equal(ga, gb)  # same kernel, same state, no atomics
+    else:
+        np.testing.assert_allclose(ga, gb, rtol=1e-12, atol=1e-9)
+    for rho in range(len(descs)):
+        assert np.array_equal(a.spins(rho), b.spins(rho))
+    assert np.array_equal(a.records(), b.records())
+    with pytest.raises(kmc.KmcError):
+        b.run(3, 1, kmc.F_GRAPH | kmc.F_SCORE)
