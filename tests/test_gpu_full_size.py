@@ -1,0 +1,153 @@
+"""Full-size workloads on the GPU (needs an MI355X).
+
+* The 4096-replica batch and the 1024-replica differentiable batch, in the
+  launch configuration the benchmark times (persistent, tuned tiles), with
+  sampled replicas checked bit-exactly against the oracle (lattices, events,
+  records; the score bins within the replay tolerance).
+* Statistics at the sizes of the single-lattice workloads: the 1024^2
+  equilibrium energy against Kaufman's exact finite-lattice value and the
+  magnetisation against Onsager/Yang below T_c; the 4096^2 quench energy
+  relaxation against serial n-fold-way kinetics (the oracle with one domain).
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from paper_1403_4674_amd import kmc, workloads
+from tests.gpu_helpers import assert_records_equal, oracle_for, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def sample_per_L(descs, per_L, rng):
+    by_L = {}
+    for i, d in enumerate(descs):
+        by_L.setdefault(d["L"], []).append(i)
+    out = []
+    for L, idx in sorted(by_L.items()):
+        out += list(rng.choice(idx, size=min(per_L, len(idx)), replace=False))
+    return sorted(int(i) for i in out)
+
+
+def test_batched_4096_sampled_parity(torch_cuda, oracle_lib):
+    seed, descs, _ = workloads.batched_4096()
+    sweeps = 12
+    say(f"4096 replicas, {sweeps} sweeps, persistent (bench configuration)")
+    lat = kmc.Lattice(descs, seed)
+    lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
+    rec = lat.records()
+    picks = sample_per_L(descs, 11, np.random.default_rng(0))
+    assert len(picks) >= 64
+    for rho in picks:
+        o = oracle_for(oracle_lib, descs[rho], seed, rho)
+        orec = o.run(sweeps, sweeps)
+        assert np.array_equal(lat.spins(rho), o.spins()), rho
+        assert_records_equal(rec[rho], orec, f"replica {rho}")
+        assert np.array_equal(lat.domain_state(rho)[2], o.domain_events())
+
+
+def test_differentiable_1024_sampled_parity(torch_cuda, oracle_lib):
+    seed, descs, _ = workloads.differentiable_1024()
+    sweeps, every = 10, 5
+    say(f"1024 replicas of 64^2 (tile {descs[0]['tile']}), fused score and replay")
+    lat = kmc.Lattice(descs, seed)
+    lat.run(sweeps, every, kmc.F_PERSISTENT | kmc.F_SCORE)
+    fused = lat.score(2)
+    rec = lat.records()
+    rep = kmc.Lattice(descs, seed)
+    rep.run(sweeps, every, kmc.F_PERSISTENT | kmc.F_CHECKPOINT)
+    replay = rep.score(2)
+    assert np.array_equal(fused, replay)
+    ticks_per_bin = every * 64 * 64
+    for rho in np.random.default_rng(1).choice(len(descs), 16, replace=False):
+        rho = int(rho)
+        o = oracle_for(oracle_lib, descs[rho], seed, rho)
+        orec, sc = o.run(sweeps, every, score=True)
+        assert np.array_equal(lat.spins(rho), o.spins()), rho
+        assert_records_equal(rec[rho], orec, f"replica {rho}")
+        np.testing.assert_allclose(fused[rho], sc, rtol=1e-10, atol=1e-11 * ticks_per_bin)
+
+
+def batch_mean(x, nb=20):
+    x = np.asarray(x, float)
+    b = x[: len(x) // nb * nb].reshape(nb, -1).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / np.sqrt(nb)
+
+
+@pytest.mark.parametrize("T,init,burn,sweeps,tol", [
+    (3.0, kmc.INIT_RANDOM, 200, 1200, 2e-4),
+    (1.5, kmc.INIT_ALL_UP, 100, 600, 2e-4),
+])
+def test_single_1024_equilibrium(torch_cuda, T, init, burn, sweeps, tol):
+    seed, descs, _ = workloads.single_1024(T)
+    d = dict(descs[0], init=init)
+    say(f"1024^2 T={T}: {burn} + {sweeps} sweeps")
+    lat = kmc.Lattice([d], seed)
+    lat.run(burn, burn, kmc.F_GRAPH)
+    lat.run(sweeps, 10, kmc.F_GRAPH)
+    rec = lat.records()[0][1:]
+    N = 1024 ** 2
+    e = -rec["B"] / N
+    m, err = batch_mean(e)
+    assert abs(m - cf.kaufman_energy(T, 1024)) < 4.5 * err + tol, (m, err)
+    if T < cf.T_CRITICAL - 0.5:
+        mm, merr = batch_mean(np.abs(rec["M"]) / N)
+        assert abs(mm - cf.onsager_magnetisation(T)) < 4.5 * merr + tol
+
+
+def test_single_1024_critical_energy_is_bracketed(torch_cuda):
+    """At T = 2.269 (2e-4 below T_c) the 1024^2 lattice relaxes over ~1e6
+    sweeps, so equilibrium is out of reach; the energy from a random (hot)
+    start must stay above Kaufman's exact value, the energy from the ordered
+    (cold) start below it, and the gap must shrink."""
+    seed, descs, _ = workloads.single_1024(2.269)
+    e_exact = cf.kaufman_energy(2.269, 1024)
+    runs = {}
+    for init in (kmc.INIT_RANDOM, kmc.INIT_ALL_UP):
+        say(f"1024^2 T=2.269 init {init}: 1500 sweeps")
+        lat = kmc.Lattice([dict(descs[0], init=init)], seed)
+        lat.run(1500, 50, kmc.F_GRAPH)
+        runs[init] = -lat.records()[0]["B"] / 1024 ** 2
+    hot, cold = runs[kmc.INIT_RANDOM], runs[kmc.INIT_ALL_UP]
+    assert (hot[3:] > e_exact).all() and (cold[3:] < e_exact).all()
+    gaps = hot - cold
+    assert gaps[-1] < 0.5 * gaps[1]
+    assert gaps[-1] < 0.05
+
+
+def test_quench_4096_relaxation_matches_serial_kinetics(torch_cuda, oracle_lib):
+    """e(t) after the quench to T = 1.5: the 4096^2 lattice in 64x64 domains
+    against the oracle with a single 128x128 domain (serial n-fold-way
+    kinetics in law), both on the simulated clock.  The paper expects the
+    decomposed dynamics to follow the serial ones closely when N_I is small
+    against the relaxation time (Sec. 3.3, Sec. 4)."""
+    seed, descs, _ = workloads.quench_4096()
+    d = descs[0]
+    sweeps = 600
+    say(f"4096^2 quench, {sweeps} sweeps")
+    lat = kmc.Lattice([d], seed)
+    lat.run(sweeps, 10, kmc.F_GRAPH)
+    rec = lat.records()[0]
+    t_gpu = rec["t"]
+    e_gpu = -rec["B"] / 4096 ** 2
+    grid = np.array([20.0, 50.0, 100.0, 200.0, 400.0])
+    assert t_gpu[-1] > grid[-1]
+    e_g = np.interp(grid, t_gpu, e_gpu)
+    # serial reference: one 128x128 domain, N_I = 1/4 sweep, several seeds
+    L = 128
+    refs = []
+    for s in range(6):
+        o = oracle_lib.Replica(L, L, T=1.5, steps_per_visit=L * L // 4, seed=100 + s)
+        r = o.run(4 * 450, 4)
+        refs.append(np.interp(grid, r["t"], -r["B"] / L ** 2))
+    refs = np.array(refs)
+    e_s, e_err = refs.mean(0), refs.std(0, ddof=1) / np.sqrt(len(refs))
+    diff = np.abs(e_g - e_s)
+    assert (diff < 4.5 * e_err + 0.01).all(), (e_g, e_s, e_err)
