@@ -74,6 +74,9 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
 #define KMC_F_SCORE 0x40u      /* accumulate the likelihood-ratio score of
                                   every tick while the run proceeds (the
                                   backward call then only copies it out)      */
+#define KMC_F_TIMING 0x80u     /* record HIP events around every launch of the
+                                  hot kernel (the phase kernel, or the
+                                  persistent kernels), read by kmc_get_timing */
 /* flags of kmc_backward_score and kmc_observables */
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
@@ -191,6 +194,12 @@ kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *clk_sum,
 /* Number of replicas, and the number of domains of one replica. */
 kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
                         int32_t *n_domains);
+
+/* Instrumentation for measuring the method's kernels, not part of it: the
+ * summed duration in milliseconds of the hot-kernel launches recorded since
+ * the last call (runs made with KMC_F_TIMING) and their number.  Events are
+ * recorded on the context stream around the launches; synchronises. */
+kmc_status kmc_get_timing(kmc_ctx *c, double *ms_total, int64_t *n_launches);
 
 /* Message of the last failed call on c (never NULL). */
 const char *kmc_last_error(const kmc_ctx *c);

@@ -112,6 +112,11 @@ struct kmc_ctx {
     int64_t pgraph_chunk = 0;
     uint32_t pgraph_key = 0;
 
+    // KMC_F_TIMING: event pairs around each hot-kernel launch
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+    std::vector<hipEvent_t> ev_pool;
+
     std::string err;
 };
 
@@ -257,9 +262,35 @@ KParams params(kmc_ctx *c) {
     return K;
 }
 
+hipEvent_t pool_event(kmc_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hip_check(c, hipEventCreate(&e), "event create");
+    return e;
+}
+
+// Brackets the launches made by fn with timing events when KMC_F_TIMING is on.
+template <typename F>
+void timed_launch(kmc_ctx *c, F fn) {
+    if (!c->timing) {
+        fn();
+        return;
+    }
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    hip_check(c, hipEventRecord(a, c->stream), "event record");
+    fn();
+    hip_check(c, hipEventRecord(b, c->stream), "event record");
+    c->tev.emplace_back(a, b);
+}
+
 template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K) {
     for (int p = 0; p < c->n_phase; ++p) {
+        timed_launch(c, [&] {
         if (c->n_tasks32) {
             K.task_begin = 0;
             hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE>), dim3(c->n_tasks32),
@@ -271,6 +302,7 @@ void launch_sweep(kmc_ctx *c, KParams K) {
                                dim3(c->n_tasks - c->n_tasks32), dim3(64), 0, c->stream, K,
                                p);
         }
+        });
     }
     hipLaunchKernelGGL(kmcdev::k_sweep_end, dim3(c->n_rep), dim3(64), 0, c->stream, K);
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, (int64_t)1);
@@ -298,19 +330,24 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t n_sweeps, uint32_t flags) 
         off += nt[g] + ns[g];
         const int groups = std::max(1, std::min(nt[g] + (ns[g] + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
-        if (g == 0)
-            hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
-                               dim3(64 * waves), 0, c->stream, K, n_sweeps);
-        else
-            hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
-                               dim3(64 * waves), 0, c->stream, K, n_sweeps);
+        timed_launch(c, [&] {
+            if (g == 0)
+                hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
+                                   dim3(64 * waves), 0, c->stream, K, n_sweeps);
+            else
+                hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
+                                   dim3(64 * waves), 0, c->stream, K, n_sweeps);
+        });
     }
     if (multi) {
         const int groups = std::max(
             1, std::min(c->n_m_wg + (c->n_m_wave + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
-        hipLaunchKernelGGL((kmcdev::k_persistent_multi<SCORE>), dim3(groups), dim3(64 * waves),
-                           0, c->stream, K, c->d_items, c->n_m_wg, c->n_m_wave, n_sweeps);
+        timed_launch(c, [&] {
+            hipLaunchKernelGGL((kmcdev::k_persistent_multi<SCORE>), dim3(groups),
+                               dim3(64 * waves), 0, c->stream, K, c->d_items, c->n_m_wg,
+                               c->n_m_wave, n_sweeps);
+        });
     }
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "persistent launch");
@@ -677,6 +714,8 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             fail(c, KMC_EINVAL, "sweep counter would exceed 2^32 - 1");
         if ((flags & KMC_F_SCORE) && (flags & KMC_F_GRAPH))
             fail(c, KMC_EINVAL, "KMC_F_SCORE is not available with KMC_F_GRAPH");
+        if ((flags & KMC_F_TIMING) && (flags & KMC_F_GRAPH))
+            fail(c, KMC_EINVAL, "KMC_F_TIMING is not available with KMC_F_GRAPH");
         if (n_sweeps == 0) return KMC_OK;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
@@ -697,6 +736,7 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             c->ck_rec_every = record_every;
             c->ck_flags = flags;
         }
+        c->timing = (flags & KMC_F_TIMING) != 0;
         KParams K = params(c);
         const bool score = (flags & KMC_F_SCORE) != 0;
         if (score || (flags & KMC_F_CHECKPOINT)) c->fused_score = false;
@@ -732,9 +772,11 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             c->fused_score = true;
             c->fused_bins = (n_sweeps + record_every - 1) / record_every;
         }
+        c->timing = false;
         c->n_rec += n_sweeps / record_every;
         c->sweep += n_sweeps;
     } catch (const Fail &f) {
+        c->timing = false;
         return f.st;
     }
     return KMC_OK;
@@ -887,6 +929,27 @@ extern "C" kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
     return KMC_OK;
 }
 
+extern "C" kmc_status kmc_get_timing(kmc_ctx *c, double *ms_total, int64_t *n_launches) {
+    if (!c) return KMC_EINVAL;
+    try {
+        hip_check(c, hipStreamSynchronize(c->stream), "timing sync");
+        double tot = 0.0;
+        for (auto &pr : c->tev) {
+            float ms = 0.0f;
+            hip_check(c, hipEventElapsedTime(&ms, pr.first, pr.second), "elapsed time");
+            tot += ms;
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        if (ms_total) *ms_total = tot;
+        if (n_launches) *n_launches = (int64_t)c->tev.size();
+        c->tev.clear();
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
 extern "C" const char *kmc_last_error(const kmc_ctx *c) {
     if (!c) return "null context";
     return c->err.c_str();
@@ -898,5 +961,10 @@ extern "C" void kmc_destroy(kmc_ctx *c) {
     if (c->graph_stream) (void)hipStreamSynchronize(c->graph_stream);
     destroy_buffers(c);
     if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
+    for (auto &pr : c->tev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }

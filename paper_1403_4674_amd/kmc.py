@@ -19,8 +19,8 @@ KMC_OK, KMC_EINVAL, KMC_ENOMEM, KMC_EDEVICE, KMC_ESTATE, KMC_EUNSUPPORTED = 0, -
 RATE_METROPOLIS, RATE_BARKER = 0, 1
 SCHED_RANDOM_PERM, SCHED_PALINDROME = 0, 1
 INIT_RANDOM, INIT_ALL_UP, INIT_GIVEN = 0, 1, 2
-F_CHECKPOINT, F_PERSISTENT, F_GRAPH, F_NO_MULTI, F_DEVICE_OUT, F_MULTI, F_SCORE = (
-    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40)
+F_CHECKPOINT, F_PERSISTENT, F_GRAPH, F_NO_MULTI, F_DEVICE_OUT, F_MULTI, F_SCORE, F_TIMING = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80)
 
 STATUS_NAMES = {0: "KMC_OK", -1: "KMC_EINVAL", -2: "KMC_ENOMEM", -3: "KMC_EDEVICE",
                 -4: "KMC_ESTATE", -5: "KMC_EUNSUPPORTED"}
@@ -68,6 +68,7 @@ def lib():
             "kmc_get_spins": ([P, I32, P], I32),
             "kmc_get_domain_state": ([P, I32, P, P, P], I32),
             "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
+            "kmc_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], I32),
             "kmc_last_error": ([P], C.c_char_p),
             "kmc_destroy": ([P], None),
         }
@@ -84,7 +85,8 @@ def exported_symbols():
     L = lib()
     names = ["kmc_set_device_allocator", "kmc_rate_table", "kmc_init_lattice",
              "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
-             "kmc_get_domain_state", "kmc_get_info", "kmc_last_error", "kmc_destroy"]
+             "kmc_get_domain_state", "kmc_get_info", "kmc_get_timing", "kmc_last_error",
+             "kmc_destroy"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -208,6 +210,15 @@ def kmc_get_domain_state(ctx, replica):
     return s, c, e
 
 
+def kmc_get_timing(ctx):
+    """(milliseconds, launches) of the hot-kernel launches timed since the
+    last call (runs with F_TIMING)."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(lib().kmc_get_timing(ctx, C.byref(ms), C.byref(n)), ctx)
+    return ms.value, n.value
+
+
 def kmc_destroy(ctx):
     if ctx:
         lib().kmc_destroy(ctx)
@@ -234,6 +245,9 @@ class Lattice:
 
     def domain_state(self, replica=0):
         return kmc_get_domain_state(self.ctx, replica)
+
+    def timing(self):
+        return kmc_get_timing(self.ctx)
 
     def score(self, n_bins, out_tensor=None):
         return kmc_backward_score(self.ctx, self.n_rep, n_bins, out_tensor)

@@ -196,3 +196,23 @@ def test_persistent_graph_replays(torch_cuda, oracle_lib):
     o = oracle_for(oracle_lib, descs[6], 31, 6)
     orec = o.run(29, 2)
     assert_replica_equal(b, 6, o, b.records()[6], orec, "graph replica 6")
+
+
+def test_timing_instrumentation_changes_nothing(torch_cuda):
+    """KMC_F_TIMING only brackets the hot-kernel launches with events: one
+    pair per phase launch (four per sweep here), results unchanged."""
+    descs = [dict(L=64, tile=16, T=2.3, h=0.1)]
+    say("timing flag")
+    a = kmc.Lattice(descs, 9)
+    b = kmc.Lattice(descs, 9)
+    a.run(6, 2)
+    b.run(6, 2, kmc.F_TIMING)
+    ms, n = b.timing()
+    assert n == 4 * 6 and ms > 0.0
+    assert b.timing() == (0.0, 0)
+    b.run(3, 3, kmc.F_PERSISTENT | kmc.F_TIMING)
+    a.run(3, 3, kmc.F_PERSISTENT)
+    ms, n = b.timing()
+    assert n >= 1 and ms > 0.0
+    assert np.array_equal(a.records(), b.records())
+    assert np.array_equal(a.spins(0), b.spins(0))
