@@ -525,6 +525,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": rate table");
             for (int k = 0; k < 10; ++k) {
                 R.inv_r[k] = R.r[k] ? (float)(1.0 / (double)R.r[k]) : 0.0f;
+                R.rd[k] = (double)R.r[k];
+                R.inv_rd[k] = R.r[k] ? 1.0 / (double)R.r[k] : 0.0;
                 R.gJ[k] = gJ[k];
                 R.gh[k] = gh[k];
                 R.aJ[k] = R.w[k] * gJ[k];

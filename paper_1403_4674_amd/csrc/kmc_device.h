@@ -50,6 +50,8 @@ struct Rates {
     uint64_t r[10];                       // Q32 rates
     float inv_r[10];                      // 1/r (0 for r = 0), for the member index
     float pad_inv[6];
+    double rd[10];                        // r as a double (exact: r <= 2^32)
+    double inv_rd[10];                    // fl(1/r) (0 for r = 0)
     double w[10], aJ[10], ah[10];         // w, w*dlnw/dJ, w*dlnw/dh
     double gJ[10], gh[10];                // dlnw/dJ, dlnw/dh
 };
@@ -245,6 +247,44 @@ __device__ __forceinline__ uint64_t rdl64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ double rdl_f64(double v, int lane) {
+    return __longlong_as_double((long long)rdl64((uint64_t)__double_as_longlong(v), lane));
+}
+
+// DPP move with bound control: lanes whose source is out of range read 0
+// (all rows and banks written, so no previous value is needed).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dppz(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dppz_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dppz<CTRL>((uint32_t)b), hi = dppz<CTRL>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Inclusive prefix sum over each 16-lane row of doubles.  Used for integer
+// rate sums below 2^53, where every addition is exact.
+__device__ __forceinline__ double scan16_f64(double v) {
+    v += dppz_f64<kRowShr + 1>(v);
+    v += dppz_f64<kRowShr + 2>(v);
+    v += dppz_f64<kRowShr + 4>(v);
+    v += dppz_f64<kRowShr + 8>(v);
+    return v;
+}
+
+// Inclusive prefix sum over lanes 0..31 (lanes 32..63 get sums of their own).
+__device__ __forceinline__ uint32_t scan32(uint32_t v) {
+    v += dpp<kRowShr + 1>(v);
+    v += dpp<kRowShr + 2>(v);
+    v += dpp<kRowShr + 4>(v);
+    v += dpp<kRowShr + 8>(v);
+    v += dpp<kRowBcast15, 0xA>(v);
+    return v;
+}
+
 __device__ __forceinline__ double rowsum16_f64(double v, int lane) {
     (void)lane;
     uint64_t b = __double_as_longlong(v);
@@ -410,6 +450,42 @@ __device__ __forceinline__ int class_at(MT S, const Planes<MT> &P, int b) {
            2 * (int)((P.s1 >> b) & 1) + 4 * (int)((P.s2 >> b) & 1);
 }
 
+// 3 * class of site b of this lane's row (the bit offset of the class's
+// field in a packed 3-bit tally word).
+template <typename MT>
+__device__ __forceinline__ uint32_t class_pos3(MT S, const Planes<MT> &P, int b) {
+    uint32_t s, p0, p1, p2;
+    if constexpr (sizeof(MT) == 8) {
+        s = (uint32_t)(S >> b);
+        p0 = (uint32_t)(P.s0 >> b);
+        p1 = (uint32_t)(P.s1 >> b);
+        p2 = (uint32_t)(P.s2 >> b);
+        b = 0;
+    } else {
+        s = S;
+        p0 = P.s0;
+        p1 = P.s1;
+        p2 = P.s2;
+    }
+    // k = k0 + 2 k1 + 4 k2, then 3 (k + 5 s)
+    const uint32_t k = __builtin_amdgcn_ubfe(p0, b, 1) | (__builtin_amdgcn_ubfe(p1, b, 1) << 1) |
+                       (__builtin_amdgcn_ubfe(p2, b, 1) << 2);
+    const uint32_t q = k + 5u * __builtin_amdgcn_ubfe(s, b, 1);
+    return q + 2u * q;
+}
+
+// Adds one (inc) or subtracts one (!inc) from the up-neighbour count k of
+// the sites in m, on the bit planes; no site overflows (k stays in 0..4).
+template <typename MT>
+__device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
+    const MT inv = inc ? (MT)0 : ~(MT)0;
+    const MT c1 = (P.s0 ^ inv) & m;
+    const MT c2 = (P.s1 ^ inv) & c1;
+    P.s0 ^= m;
+    P.s1 ^= c1;
+    P.s2 ^= c2;
+}
+
 struct VisitOut {
     int64_t events;
     int64_t dM, dB;
@@ -481,12 +557,15 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         if (lane == c) n_lane = tot & 0xFFFFu;
         if (lane == c + 1) n_lane = tot >> 16;
     }
-    const uint64_t r_lane = lane < 10 ? rt->r[lane] : 0;
-    const float inv_lane = lane < 10 ? rt->inv_r[lane] : 0.0f;
-    const int lane3 = 3 * lane;
-    uint64_t W = (uint64_t)n_lane * r_lane;
-    uint64_t Pinc = scan16_dpp(W);
-    uint64_t R = rdl64(Pinc, 9);
+    // Rate sums are integers below n_d 2^32 <= 2^44, held in doubles: every
+    // sum, difference, product n_c * r_c and comparison below is exact.
+    const double rd_lane = lane < 10 ? rt->rd[lane] : 0.0;
+    const double inv_lane = lane < 10 ? rt->inv_rd[lane] : 0.0;
+    const uint32_t lane3 = lane < 10 ? 3u * lane : 30u;  // tally field (30: always 0)
+    double W = (double)n_lane * rd_lane;
+    double Pinc = scan16_f64(W);
+    double R = rdl_f64(Pinc, 9);
+    const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
 
     double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
     if constexpr (SCORE) {
@@ -500,6 +579,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
+    uint32_t ev_lane = 0;                  // lanes 0..9: events of class c = lane
     double clk_sum = 0.0, clk_comp = 0.0;  // this lane's events' residence times
     uint32_t m_null = 0;                   // null ticks since the last event (score)
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
@@ -534,107 +614,115 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                 rej = (uint32_t)mm < thr;
             }
         }
-        const uint64_t x = ((mm >> 32) << 32) | o.x;
-        const uint64_t vmask = __ballot(valid);
-        uint64_t Rb = 0;  // this lane's R before its event (0: no event)
+        // x = slot 2^32 + w0, exact in a double
+        const double x = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x;
+        uint64_t left = __ballot(valid);  // ticks of the batch not yet decided
+        double Rb = 0.0;                  // this lane's R before its event (0: none)
         int pos = 0;
         for (;;) {
-            const uint64_t lanes_left = pos >= 64 ? 0 : (vmask >> pos) << pos;
-            const uint64_t cand = __ballot(x < R) & lanes_left;
+            const uint64_t cand = __ballot(x < R) & left;
             if (!cand) {
-                m_null += (uint32_t)__popcll(lanes_left);
+                m_null += (uint32_t)__popcll(left);
                 break;
             }
-            const int e = __ffsll((long long)cand) - 1;
+            const int e = __builtin_ctzll(cand);
+            left &= ~(cand ^ (cand - 1));  // drop the ticks up to and including e
             m_null += (uint32_t)(e - pos);
-            const uint64_t xe = rdl64(x, e);
+            const double xe = rdl_f64(x, e);
             if (lane == e) Rb = R;
 
-            // rate class: first c with xe < P_c; member index j =
-            // floor((xe - P_{c-1}) / r_c), formed in every class lane at
-            // once: FP32 estimate (error < 1) and one exact integer correction
-            const int c = __ffsll((long long)__ballot(lane < 10 && xe < Pinc)) - 1;
-            const uint64_t Pexc = Pinc - W;
-            const uint64_t a = xe >= Pexc ? xe - Pexc : 0;
-            const float af = (float)(uint32_t)(a >> 32) * 4294967296.0f + (float)(uint32_t)a;
-            const uint32_t j0 = (uint32_t)(af * inv_lane);
-            const uint64_t tj = (uint64_t)j0 * r_lane;
-            const uint32_t jl = j0 - (tj > a ? 1u : 0u) + (tj + r_lane <= a ? 1u : 0u);
+            // rate class: first c with xe < P_c (lane 9 holds R > xe).  Member
+            // index j = floor((xe - P_{c-1}) / r_c), formed in every class lane
+            // at once as trunc((xe - P_{c-1} + 1/2) fl(1/r_c)): the quotient
+            // lies at least 1/(2 r_c) >= 2^-33 from an integer and the product
+            // is within 2^-39 of it (quotient < 2^13), so the truncation is
+            // exact; other lanes are clamped into range and discarded.
+            const int c = __builtin_ctzll(__ballot(xe < Pinc));
+            const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
+            const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
             const uint32_t j = rdl32(jl, c);
 
             if constexpr (SCORE) {
                 if (m_null) null_score(m_null);
-                out.sJ += __longlong_as_double((long long)rdl64(__double_as_longlong(gJ_lane), c));
-                out.sh += __longlong_as_double((long long)rdl64(__double_as_longlong(gh_lane), c));
+                out.sJ += rdl_f64(gJ_lane, c);
+                out.sh += rdl_f64(gh_lane, c);
             }
             m_null = 0;
 
             // member j of class c in ascending row-major order: the row by a
-            // 64-lane scan of per-row counts, the column by counting the
-            // row's members below each lane (mbcnt)
+            // scan of per-row counts, the column by counting the row's
+            // members below each lane (mbcnt)
             const MT cm = class_mask<MT>(c, S, P, VM);
             const uint32_t cnt = (uint32_t)popc(cm);
-            const uint32_t incl = scan64(cnt);
-            const int ys = __ffsll((long long)__ballot(incl > j)) - 1;
+            const uint32_t incl = sizeof(MT) == 4 ? scan32(cnt) : scan64(cnt);
+            const int ys = __builtin_ctzll(__ballot(incl > j));
             const uint32_t jr = j - rdl32(incl - cnt, ys);
-            uint64_t row = (uint64_t)rdl32((uint32_t)cm, ys);
-            if constexpr (sizeof(MT) == 8) row |= (uint64_t)rdl32((uint32_t)(cm >> 32), ys) << 32;
-            const int xs = __ffsll((long long)(__ballot(bits_below_lane(row) == jr) & row)) - 1;
+            int xs;
+            if constexpr (sizeof(MT) == 8) {
+                const uint64_t row = rdl64(cm, ys);
+                xs = __builtin_ctzll(__ballot(bits_below_lane(row) == jr) & row);
+            } else {
+                const uint32_t row = rdl32(cm, ys);
+                xs = __builtin_ctzll(
+                    __ballot(__builtin_amdgcn_mbcnt_lo(row, 0u) == jr) & (uint64_t)row);
+            }
 
-            // class changes of the flipped site and its in-tile neighbours,
-            // as packed 3-bit per-class tallies (10 classes in 30 bits)
+            // class changes of the flipped site and its in-tile neighbours as
+            // packed 3-bit per-class tallies (10 classes in 30 bits): row ys
+            // holds the sites at columns xs -/+ 1, rows ys -/+ 1 the site at
+            // column xs; the three rows are summed into row ys by DPP
             const bool up = c >= 5;
-            const int k = up ? c - 5 : c;
-            const int delta = up ? -1 : 1;
-            const int xl = xs > 0 ? xs - 1 : xs, xr = xs < B - 1 ? xs + 1 : xs;
-            const int cls_mid = class_at<MT>(S, P, xs);
-            const int cls_l = class_at<MT>(S, P, xl);
-            const int cls_r = class_at<MT>(S, P, xr);
-            uint32_t add = 1u << (3 * (up ? c - 5 : c + 5));
-            uint32_t sub = 1u << (3 * c);
-            if (ys > 0) {
-                const int q = (int)rdl32((uint32_t)cls_mid, ys - 1);
-                sub += 1u << (3 * q);
-                add += 1u << (3 * (q + delta));
-            }
-            if (ys < B - 1) {
-                const int q = (int)rdl32((uint32_t)cls_mid, ys + 1);
-                sub += 1u << (3 * q);
-                add += 1u << (3 * (q + delta));
-            }
-            if (xs > 0) {
-                const int q = (int)rdl32((uint32_t)cls_l, ys);
-                sub += 1u << (3 * q);
-                add += 1u << (3 * (q + delta));
-            }
-            if (xs < B - 1) {
-                const int q = (int)rdl32((uint32_t)cls_r, ys);
-                sub += 1u << (3 * q);
-                add += 1u << (3 * (q + delta));
-            }
-            if (lane < 10)
-                n_lane = n_lane + ((add >> lane3) & 7u) - ((sub >> lane3) & 7u);
-            W = (uint64_t)n_lane * r_lane;
-            Pinc = scan16_dpp(W);
-            R = rdl64(Pinc, 9);
+            const int c_new = up ? c - 5 : c + 5;
+            const bool on_row = lane == ys;
+            const bool adj = (lane == ys - 1 || lane == ys + 1) && lane < B;
+            constexpr int NB = 8 * (int)sizeof(MT);
+            const int ca = on_row ? xs - 1 : xs;
+            const bool va = on_row ? xs > 0 : adj;
+            const bool vb = on_row && xs < B - 1;
+            const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
+            const uint32_t pb = class_pos3<MT>(S, P, (xs + 1) & (NB - 1));
+            uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+            nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
+            const uint32_t nb_s = rdl32(nb, ys);
+            // every neighbour moves one class up (flip to +1) or down: the
+            // whole tally shifts by one field (no class leaves its spin's range)
+            const uint32_t sub_s = nb_s + (1u << (3 * c));
+            const uint32_t add_s =
+                (uint32_t)(((uint64_t)nb_s << 3) >> (up ? 6 : 0)) + (1u << (3 * c_new));
+            n_lane = n_lane + ((add_s >> lane3) & 7u) - ((sub_s >> lane3) & 7u);
+            ev_lane += lane == c ? 1u : 0u;
+            W = (double)n_lane * rd_lane;
+            Pinc = scan16_f64(W);
+            R = rdl_f64(Pinc, 9);
 
-            if (lane == ys) S ^= (MT)1 << xs;
-            P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
-
-            out.dM += up ? -2 : 2;
-            out.dB += (up ? -2 : 2) * (2 * k - 4);
-            ++out.events;
+            // flip, and move the neighbours' up-counts on the bit planes
+            const MT bx = (MT)1 << xs;
+            const MT mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+            if (on_row) S ^= bx;
+            planes_step<MT>(P, on_row ? mrow : (adj ? bx : (MT)0), !up);
             pos = e + 1;
         }
-        // residence times -ln(u)/R_w of this batch's events, kept per lane
-        if (Rb) {
+        // residence times -ln(u)/R of this batch's events, kept per lane
+        if (Rb != 0.0) {
             const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
             const double u = (double)(u53 + 1) * 0x1p-53;
-            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / (double)Rb);
+            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / Rb);
         }
     }
     if constexpr (SCORE) {
         if (m_null) null_score(m_null);
+    }
+    {
+        // events, dM and dB from the per-class event counts: a flip of class
+        // c = 5 [s=+1] + k changes M by -2s and the bond sum by -2s (2k - 4)
+#pragma unroll
+        for (int cc = 0; cc < 10; ++cc) {
+            const int64_t n = (int64_t)rdl32(ev_lane, cc);
+            const int64_t m2 = cc >= 5 ? -2 : 2;
+            out.events += n;
+            out.dM += m2 * n;
+            out.dB += m2 * (2 * (cc % 5) - 4) * n;
+        }
     }
     {
         double cs = clk_sum, cc = clk_comp;
