@@ -524,7 +524,6 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             if (rate_table(q.J, q.h, q.T, q.rate_model, R.r, R.w, gJ, gh) != KMC_OK)
                 fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": rate table");
             for (int k = 0; k < 10; ++k) {
-                R.inv_r[k] = R.r[k] ? (float)(1.0 / (double)R.r[k]) : 0.0f;
                 R.rd[k] = (double)R.r[k];
                 R.inv_rd[k] = R.r[k] ? 1.0 / (double)R.r[k] : 0.0;
                 R.gJ[k] = gJ[k];

@@ -48,8 +48,6 @@ constexpr int kWavesPerPersistentGroup = 4;
 
 struct Rates {
     uint64_t r[10];                       // Q32 rates
-    float inv_r[10];                      // 1/r (0 for r = 0), for the member index
-    float pad_inv[6];
     double rd[10];                        // r as a double (exact: r <= 2^32)
     double inv_rd[10];                    // fl(1/r) (0 for r = 0)
     double w[10], aJ[10], ah[10];         // w, w*dlnw/dJ, w*dlnw/dh

@@ -39,13 +39,12 @@ __device__ __forceinline__ uint64_t sbc64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t seg16(uint64_t m, int slot) {
-    return (uint32_t)(m >> (16 * slot)) & 0xFFFFu;
+__device__ __forceinline__ double sbc_f64(double v, int src) {
+    return __longlong_as_double((long long)sbc64((uint64_t)__double_as_longlong(v), src));
 }
 
-// lowest set bit of a nonzero 16-bit segment (16 when empty)
-__device__ __forceinline__ int low16(uint32_t seg) {
-    return seg ? __builtin_ctz(seg) : 16;
+__device__ __forceinline__ uint32_t seg16(uint64_t m, int slot) {
+    return (uint32_t)(m >> (16 * slot)) & 0xFFFFu;
 }
 
 // Inclusive prefix sum inside each 16-lane row.
@@ -161,12 +160,14 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
         if (sl == c) n_lane = tot & 0xFFFFu;
         if (sl == c + 1) n_lane = tot >> 16;
     }
-    const uint64_t r_lane = (A.on && sl < 10) ? rt->r[sl] : 0;
-    const float inv_lane = (A.on && sl < 10) ? rt->inv_r[sl] : 0.0f;
-    const int sl3 = 3 * sl;
-    uint64_t W = (uint64_t)n_lane * r_lane;
-    uint64_t Pinc = scan16_dpp(W);
-    uint64_t R = sbc64(Pinc, base + 9);
+    // exact FP64 rate sums (integers below 2^44), as in visit_domain
+    const double rd_lane = (A.on && sl < 10) ? rt->rd[sl] : 0.0;
+    const double inv_lane = (A.on && sl < 10) ? rt->inv_rd[sl] : 0.0;
+    const uint32_t sl3 = sl < 10 ? 3u * (uint32_t)sl : 30u;  // tally field (30: always 0)
+    double W = (double)n_lane * rd_lane;
+    double Pinc = scan16_f64(W);
+    double R = sbc_f64(Pinc, base + 9);
+    const uint32_t vm_row = (1u << B) - 1u;
 
     double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
     if constexpr (SCORE) {
@@ -180,6 +181,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
+    uint32_t ev_lane = 0;  // lanes 0..9 of a slot: events of class c = lane
     double clk_sum = 0.0, clk_comp = 0.0;
     uint32_t m_null = 0;
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
@@ -212,42 +214,36 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
                 rej = (uint32_t)mm < thr;
             }
         }
-        const uint64_t x = ((mm >> 32) << 32) | o.x;
-        const uint32_t vseg = seg16(__ballot(valid), slot);
-        uint64_t Rb = 0;
+        const double x = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x;
+        uint32_t left = seg16(__ballot(valid), slot);  // the slot's undecided ticks
+        double Rb = 0.0;
         int pos = 0;
-        bool done = !A.on;
         for (;;) {
-            const uint32_t left = pos >= 16 ? 0u : (vseg >> pos) << pos;
-            const uint32_t cseg = done ? 0u : seg16(__ballot(x < R), slot) & left;
-            if (!done && !cseg) {  // the slot's batch has no further event
-                m_null += (uint32_t)__popc(left);
-                done = true;
-            }
+            // a slot without a further event in this batch adds its
+            // remaining nulls once: its `left` is cleared below
+            const uint32_t cseg = seg16(__ballot(x < R), slot) & left;
+            if (!cseg) m_null += (uint32_t)__popc(left);
             const bool act = cseg != 0;
             if (!__ballot(act)) break;
-            const int e = act ? low16(cseg) : 0;
+            const int e = act ? __builtin_ctz(cseg) : 0;
+            left &= ~(cseg ^ (cseg - 1u));
             if (act) m_null += (uint32_t)(e - pos);
-            const uint64_t xe = sbc64(x, base + e);
+            const double xe = sbc_f64(x, base + e);
             if (act && sl == e) Rb = R;
 
-            // rate class and member index (class lanes of each slot)
-            const int c = act ? low16(seg16(__ballot(sl < 10 && xe < Pinc), slot)) : 0;
-            const uint64_t Pexc = Pinc - W;
-            const uint64_t a = xe >= Pexc ? xe - Pexc : 0;
-            const float af = (float)(uint32_t)(a >> 32) * 4294967296.0f + (float)(uint32_t)a;
-            const uint32_t j0 = (uint32_t)(af * inv_lane);
-            const uint64_t tj = (uint64_t)j0 * r_lane;
-            const uint32_t jl = j0 - (tj > a ? 1u : 0u) + (tj + r_lane <= a ? 1u : 0u);
+            // rate class and member index (class lanes of each slot; the
+            // FP64 index is exact, see visit_domain)
+            const uint32_t cseg_c = seg16(__ballot(xe < Pinc), slot);
+            const int c = act ? __builtin_ctz(cseg_c) : 0;
+            const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
+            const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
             const uint32_t j = sbc32(jl, base + c);
 
             if constexpr (SCORE) {
                 null_score(m_null, act);
                 if (act) {
-                    out.sJ += __longlong_as_double((long long)sbc64(__double_as_longlong(gJ_lane),
-                                                                    base + c));
-                    out.sh += __longlong_as_double((long long)sbc64(__double_as_longlong(gh_lane),
-                                                                    base + c));
+                    out.sJ += sbc_f64(gJ_lane, base + c);
+                    out.sh += sbc_f64(gh_lane, base + c);
                 }
             }
             if (act) m_null = 0;
@@ -256,66 +252,62 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             const uint32_t cm = class_mask<uint32_t>(c, S, P, VM);
             const uint32_t cnt = (uint32_t)__popc(cm);
             const uint32_t incl = scan_row(cnt);
-            const int ys = act ? low16(seg16(__ballot(incl > j), slot)) : 0;
+            const uint32_t yseg = seg16(__ballot(incl > j), slot);
+            const int ys = act ? __builtin_ctz(yseg) : 0;
             const uint32_t jr = j - sbc32(incl - cnt, base + ys);
             const uint32_t rowm = sbc32(cm, base + ys);
             const uint32_t rank = (uint32_t)__popc(rowm & ((1u << sl) - 1u));
-            const int xs =
-                act ? low16(seg16(__ballot(((rowm >> sl) & 1u) && rank == jr), slot)) : 0;
+            const uint32_t xseg = seg16(__ballot(((rowm >> sl) & 1u) && rank == jr), slot);
+            const int xs = act ? __builtin_ctz(xseg) : 0;
 
-            // class tallies of the flipped site and its in-tile neighbours
+            // packed class tallies of the flipped site and its in-tile
+            // neighbours, the three rows summed inside the slot by DPP
             const bool up = c >= 5;
-            const int k = up ? c - 5 : c;
-            const int delta = up ? -1 : 1;
-            const int xl = xs > 0 ? xs - 1 : xs, xr = xs < B - 1 ? xs + 1 : xs;
-            const int cls_mid = class_at<uint32_t>(S, P, xs);
-            const int cls_l = class_at<uint32_t>(S, P, xl);
-            const int cls_r = class_at<uint32_t>(S, P, xr);
-            const int qu = (int)sbc32((uint32_t)cls_mid, base + (ys > 0 ? ys - 1 : 0));
-            const int qd = (int)sbc32((uint32_t)cls_mid, base + (ys < B - 1 ? ys + 1 : ys));
-            const int ql = (int)sbc32((uint32_t)cls_l, base + ys);
-            const int qr = (int)sbc32((uint32_t)cls_r, base + ys);
-            uint32_t add = 1u << (3 * (up ? c - 5 : c + 5));
-            uint32_t sub = 1u << (3 * c);
-            if (ys > 0) {
-                sub += 1u << (3 * qu);
-                add += 1u << (3 * (qu + delta));
-            }
-            if (ys < B - 1) {
-                sub += 1u << (3 * qd);
-                add += 1u << (3 * (qd + delta));
-            }
-            if (xs > 0) {
-                sub += 1u << (3 * ql);
-                add += 1u << (3 * (ql + delta));
-            }
-            if (xs < B - 1) {
-                sub += 1u << (3 * qr);
-                add += 1u << (3 * (qr + delta));
-            }
-            if (act && sl < 10)
-                n_lane = n_lane + ((add >> sl3) & 7u) - ((sub >> sl3) & 7u);
-            W = (uint64_t)n_lane * r_lane;
-            Pinc = scan16_dpp(W);
-            R = sbc64(Pinc, base + 9);
-
-            if (act && sl == ys) S ^= 1u << xs;
-            P = planes(S);
+            const int c_new = up ? c - 5 : c + 5;
+            const bool on_row = sl == ys;
+            const bool adj = (sl == ys - 1 || sl == ys + 1) && sl < B;
+            const int ca = on_row ? xs - 1 : xs;
+            const bool va = on_row ? xs > 0 : adj;
+            const bool vb = on_row && xs < B - 1;
+            const uint32_t pa = class_pos3<uint32_t>(S, P, ca & 31);
+            const uint32_t pb = class_pos3<uint32_t>(S, P, (xs + 1) & 31);
+            uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+            nb += dppz<kRowShr + 1>(nb) + dppz<kRowShl1>(nb);
+            const uint32_t nb_s = sbc32(nb, base + ys);
+            const uint32_t sub_s = nb_s + (1u << (3 * c));
+            const uint32_t add_s =
+                (uint32_t)(((uint64_t)nb_s << 3) >> (up ? 6 : 0)) + (1u << (3 * c_new));
             if (act) {
-                out.dM += up ? -2 : 2;
-                out.dB += (up ? -2 : 2) * (2 * k - 4);
-                ++out.events;
-                pos = e + 1;
+                n_lane = n_lane + ((add_s >> sl3) & 7u) - ((sub_s >> sl3) & 7u);
+                ev_lane += sl == c ? 1u : 0u;
             }
+            W = (double)n_lane * rd_lane;
+            Pinc = scan16_f64(W);
+            R = sbc_f64(Pinc, base + 9);
+
+            const uint32_t bx = 1u << xs;
+            const uint32_t mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+            if (act && on_row) S ^= bx;
+            planes_step<uint32_t>(P, act ? (on_row ? mrow : (adj ? bx : 0u)) : 0u, !up);
+            if (act) pos = e + 1;
         }
-        if (Rb) {
+        if (Rb != 0.0) {
             const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
             const double u = (double)(u53 + 1) * 0x1p-53;
-            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / (double)Rb);
+            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / Rb);
         }
     }
     if constexpr (SCORE) {
         null_score(m_null, A.on);
+    }
+    // events, dM and dB of each slot from its per-class event counts
+#pragma unroll
+    for (int cc = 0; cc < 10; ++cc) {
+        const int64_t n = (int64_t)sbc32(ev_lane, base + cc);
+        const int64_t m2 = cc >= 5 ? -2 : 2;
+        out.events += n;
+        out.dM += m2 * n;
+        out.dB += m2 * (2 * (cc % 5) - 4) * n;
     }
     {
         const double cs = sum_row_f64(clk_sum, base);
