@@ -283,20 +283,11 @@ __device__ __forceinline__ uint32_t scan32(uint32_t v) {
     return v;
 }
 
+// Total of lanes 0..15 (the last element of the row scan; the multi-slot
+// kernel sums in the same order, so the two agree bit for bit).
 __device__ __forceinline__ double rowsum16_f64(double v, int lane) {
     (void)lane;
-    uint64_t b = __double_as_longlong(v);
-#pragma unroll
-    for (int sft = 1; sft < 16; sft <<= 1) {
-        const uint64_t t = sft == 1 ? dpp_any<kRowShr + 1>(b)
-                         : sft == 2 ? dpp_any<kRowShr + 2>(b)
-                         : sft == 4 ? dpp_any<kRowShr + 4>(b)
-                                    : dpp_any<kRowShr + 8>(b);
-        b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(t));
-    }
-    const uint64_t tot = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), 15) << 32) |
-                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 15);
-    return __longlong_as_double(tot);
+    return rdl_f64(scan16_f64(v), 15);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
@@ -583,18 +574,17 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
 
-    auto null_score = [&](uint32_t m) {
-        // d ln(1 - R_w/n_d)/d theta per null tick, times m
+    // Score.  A run of m null ticks adds m d ln(1 - R_w/n_d)/d theta =
+    // -m sum_c n_c a_c / (n_d - R_w) (a_c = w_c d ln w_c/d theta), linear in
+    // the counts: class lane c accumulates A_c = sum over runs of
+    // m n_c / (n_d - R_w), and the visit's score is
+    // sum_c (events_c g_c - a_c A_c), formed once at the end.
+    double A_lane = 0.0;
+    auto null_run = [&](uint32_t m) {
         const double nl = (double)n_lane;
         const double Rw = rowsum16_f64(nl * w_lane, lane);
-        const double RJ = rowsum16_f64(nl * aJ_lane, lane);
-        const double Rh = rowsum16_f64(nl * ah_lane, lane);
         const double den = (double)nd - Rw;
-        if (den > 0.0) {
-            const double md = (double)m / den;
-            out.sJ -= md * RJ;
-            out.sh -= md * Rh;
-        }
+        if (den > 0.0) A_lane += ((double)m / den) * nl;
     };
 
     for (int base = 0; base < NI; base += 64) {
@@ -641,9 +631,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             const uint32_t j = rdl32(jl, c);
 
             if constexpr (SCORE) {
-                if (m_null) null_score(m_null);
-                out.sJ += rdl_f64(gJ_lane, c);
-                out.sh += rdl_f64(gh_lane, c);
+                if (m_null) null_run(m_null);
             }
             m_null = 0;
 
@@ -708,7 +696,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         }
     }
     if constexpr (SCORE) {
-        if (m_null) null_score(m_null);
+        if (m_null) null_run(m_null);
+        const double ev = (double)ev_lane;
+        out.sJ = rowsum16_f64(gJ_lane * ev - aJ_lane * A_lane, lane);
+        out.sh = rowsum16_f64(gh_lane * ev - ah_lane * A_lane, lane);
     }
     {
         // events, dM and dB from the per-class event counts: a flip of class

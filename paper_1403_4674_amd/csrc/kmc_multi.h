@@ -57,16 +57,7 @@ __device__ __forceinline__ uint32_t scan_row(uint32_t v) {
 }
 
 __device__ __forceinline__ double sum_row_f64(double v, int base) {
-    uint64_t b = __double_as_longlong(v);
-    b = __double_as_longlong(__longlong_as_double(b) +
-                             __longlong_as_double(dpp_any<kRowShr + 1>(b)));
-    b = __double_as_longlong(__longlong_as_double(b) +
-                             __longlong_as_double(dpp_any<kRowShr + 2>(b)));
-    b = __double_as_longlong(__longlong_as_double(b) +
-                             __longlong_as_double(dpp_any<kRowShr + 4>(b)));
-    b = __double_as_longlong(__longlong_as_double(b) +
-                             __longlong_as_double(dpp_any<kRowShr + 8>(b)));
-    return __longlong_as_double((long long)sbc64(b, base + 15));
+    return sbc_f64(scan16_f64(v), base + 15);
 }
 
 constexpr int kRowShl1 = 0x101;  // lane i <- lane i+1 inside a row
@@ -187,17 +178,13 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = A.d | (vis << 20) | (kStreamTick << 24);
 
-    auto null_score = [&](uint32_t m, bool act) {
+    // score: per-class accumulation of the null runs, as in visit_domain
+    double A_lane = 0.0;
+    auto null_run = [&](uint32_t m, bool act) {
         const double nl = (double)n_lane;
         const double Rw = sum_row_f64(nl * w_lane, base);
-        const double RJ = sum_row_f64(nl * aJ_lane, base);
-        const double Rh = sum_row_f64(nl * ah_lane, base);
         const double den = (double)nd - Rw;
-        if (act && m && den > 0.0) {
-            const double md = (double)m / den;
-            out.sJ -= md * RJ;
-            out.sh -= md * Rh;
-        }
+        if (act && m && den > 0.0) A_lane += ((double)m / den) * nl;
     };
 
     for (int b0 = 0; b0 < NI; b0 += kSlotW) {
@@ -240,11 +227,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             const uint32_t j = sbc32(jl, base + c);
 
             if constexpr (SCORE) {
-                null_score(m_null, act);
-                if (act) {
-                    out.sJ += sbc_f64(gJ_lane, base + c);
-                    out.sh += sbc_f64(gh_lane, base + c);
-                }
+                if (__ballot(act && m_null)) null_run(m_null, act);
             }
             if (act) m_null = 0;
 
@@ -298,7 +281,10 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
         }
     }
     if constexpr (SCORE) {
-        null_score(m_null, A.on);
+        null_run(m_null, A.on);
+        const double ev = (double)ev_lane;
+        out.sJ = sum_row_f64(gJ_lane * ev - aJ_lane * A_lane, base);
+        out.sh = sum_row_f64(gh_lane * ev - ah_lane * A_lane, base);
     }
     // events, dM and dB of each slot from its per-class event counts
 #pragma unroll
