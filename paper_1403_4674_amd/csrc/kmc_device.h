@@ -422,15 +422,20 @@ __device__ __forceinline__ Planes<MT> neighbour_planes(MT S, MT top, MT bot,
     return P;
 }
 
+// Sites of class c = 5 [s=+1] + k among this lane's row.  Each plane is
+// taken as is or complemented; bit c of these tables says "complement"
+// (s = -1 for c < 5; k0, k1, k2 = 0), expanded to all ones by 0 - bit.
+// (The signed bit-field builtin is avoided: the compiler takes its result
+// for non-negative and drops the upper word of a 64-bit extension.)
+constexpr uint32_t kInvS = 0x01F, kInvK0 = 0x2B5, kInvK1 = 0x273, kInvK2 = 0x1EF;
+
 template <typename MT>
 __device__ __forceinline__ MT class_mask(int c, MT S, const Planes<MT> &P, MT VM) {
-    const bool up = c >= 5;
-    const int k = up ? c - 5 : c;
-    MT m = up ? S : ~S;
-    m &= (k & 1) ? P.s0 : ~P.s0;
-    m &= (k & 2) ? P.s1 : ~P.s1;
-    m &= (k & 4) ? P.s2 : ~P.s2;
-    return m & VM;
+    const MT xS = (MT)0 - (MT)__builtin_amdgcn_ubfe(kInvS, c, 1);
+    const MT x0 = (MT)0 - (MT)__builtin_amdgcn_ubfe(kInvK0, c, 1);
+    const MT x1 = (MT)0 - (MT)__builtin_amdgcn_ubfe(kInvK1, c, 1);
+    const MT x2 = (MT)0 - (MT)__builtin_amdgcn_ubfe(kInvK2, c, 1);
+    return (S ^ xS) & (P.s0 ^ x0) & (P.s1 ^ x1) & (P.s2 ^ x2) & VM;
 }
 
 template <typename MT>

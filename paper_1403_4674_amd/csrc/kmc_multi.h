@@ -159,6 +159,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     double Pinc = scan16_f64(W);
     double R = sbc_f64(Pinc, base + 9);
     const uint32_t vm_row = (1u << B) - 1u;
+    const uint32_t upto_lane = (2u << sl) - 1u;  // bits 0..sl
 
     double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
     if constexpr (SCORE) {
@@ -212,7 +213,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             if (!cseg) m_null += (uint32_t)__popc(left);
             const bool act = cseg != 0;
             if (!__ballot(act)) break;
-            const int e = act ? __builtin_ctz(cseg) : 0;
+            const int e = __builtin_ctz(cseg | 0x10000u);  // 16 when idle
             left &= ~(cseg ^ (cseg - 1u));
             if (act) m_null += (uint32_t)(e - pos);
             const double xe = sbc_f64(x, base + e);
@@ -221,7 +222,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // rate class and member index (class lanes of each slot; the
             // FP64 index is exact, see visit_domain)
             const uint32_t cseg_c = seg16(__ballot(xe < Pinc), slot);
-            const int c = act ? __builtin_ctz(cseg_c) : 0;
+            const int c = __builtin_ctz(cseg_c | 0x10000u);
             const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
             const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
             const uint32_t j = sbc32(jl, base + c);
@@ -236,12 +237,14 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             const uint32_t cnt = (uint32_t)__popc(cm);
             const uint32_t incl = scan_row(cnt);
             const uint32_t yseg = seg16(__ballot(incl > j), slot);
-            const int ys = act ? __builtin_ctz(yseg) : 0;
+            const int ys = __builtin_ctz(yseg | 0x10000u);
             const uint32_t jr = j - sbc32(incl - cnt, base + ys);
             const uint32_t rowm = sbc32(cm, base + ys);
-            const uint32_t rank = (uint32_t)__popc(rowm & ((1u << sl) - 1u));
-            const uint32_t xseg = seg16(__ballot(((rowm >> sl) & 1u) && rank == jr), slot);
-            const int xs = act ? __builtin_ctz(xseg) : 0;
+            // the column: the first lane whose count of members up to and
+            // including it exceeds jr
+            const uint32_t rank_incl = (uint32_t)__popc(rowm & upto_lane);
+            const uint32_t xseg = seg16(__ballot(rank_incl > jr), slot);
+            const int xs = __builtin_ctz(xseg | 0x10000u);
 
             // packed class tallies of the flipped site and its in-tile
             // neighbours, the three rows summed inside the slot by DPP
