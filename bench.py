@@ -32,6 +32,30 @@ OPS_PER_EVENT = 64
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer lane-operations/s
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
+# HBM bytes of one phase-kernel launch of the plain workload: rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
+# counter reads for a 1 GiB device copy (profiles/copy_calibration_1GiB.md,
+# profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
+# kernel source the counters were taken on; reported as null otherwise.
+PLAIN_TRAFFIC = {
+    "kernel_source_sha256": "ce411f87dd45cadd6595320ced74a0f1d60b91ff223b9ac610adc2f61193a7b8",
+    "fetch_kib": 911.5, "fetch_scale": 1048576.0 / 524308.19,
+    "write_kib": 288.0, "write_scale": 1048576.0 / 1048576.0,
+}
+# algorithmic bytes per plain launch: each of the 256 domains reads its
+# 32x32 int8 tile and 4 x 32 halo sites and writes the tile back
+PLAIN_ALG_BYTES = 256 * (2 * 32 * 32 + 4 * 32)
+
+
+def plain_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", "kmc_device.h")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != PLAIN_TRAFFIC["kernel_source_sha256"]:
+            return None
+    t = PLAIN_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
 
 def timed(fn, stream):
     import torch
@@ -80,11 +104,16 @@ def batched(args, kmc, workloads):
     lat = kmc.Lattice(descs, seed)
     stream = torch.cuda.current_stream()
     lat.run(2, 1, kmc.F_PERSISTENT | args.flags)
-    sec = timed(lambda: lat.run(args.batched_sweeps, args.batched_sweeps,
-                                kmc.F_PERSISTENT | args.flags), stream)
+    ev0 = int(lat.records()["events"][:, -1].sum())
+    lat.timing()
+    flags = kmc.F_PERSISTENT | kmc.F_TIMING | args.flags
+    sec = timed(lambda: lat.run(args.batched_sweeps, args.batched_sweeps, flags), stream)
+    kernel_ms, launches = lat.timing()
+    events = int(lat.records()["events"][:, -1].sum()) - ev0
     ticks = args.batched_sweeps * sum(x["L"] ** 2 for x in descs)
     lat.close()
-    return dict(sec=sec, ticks=ticks, replicas=len(descs), sweeps=args.batched_sweeps)
+    return dict(sec=sec, ticks=ticks, events=events, replicas=len(descs),
+                sweeps=args.batched_sweeps, kernel_sec=kernel_ms / 1e3, launches=launches)
 
 
 def backward(args, kmc, workloads):
@@ -242,7 +271,9 @@ def main():
             "peak": ALU_PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / ALU_PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": plain_traffic(),
+            "traffic_unit": "B/launch",
+            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES,
             "per_launch_ms": per_launch * 1e3,
             "launches": p["launches"],
             "ops_per_launch": ops / p["launches"],
@@ -253,9 +284,16 @@ def main():
     if args.mode == "all":
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
+        b_ops = OPS_PER_TICK * b["ticks"] + OPS_PER_EVENT * b["events"]
         line["batched"] = {"value": b["ticks"] / b["sec"], "unit": "site-updates/s",
                            "replicas": b["replicas"], "sweeps": b["sweeps"],
-                           "vs_plain": (b["ticks"] / b["sec"]) / value}
+                           "vs_plain": (b["ticks"] / b["sec"]) / value,
+                           "roofline": {"bound": "alu", "kernel": "k_persistent_multi<false>",
+                                        "achieved": b_ops / b["kernel_sec"] / 1e12,
+                                        "peak": ALU_PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                                        "frac": b_ops / b["kernel_sec"] / ALU_PEAK_LANE_OPS,
+                                        "per_launch_ms": b["kernel_sec"] * 1e3 / b["launches"],
+                                        "launches": b["launches"]}}
         line["backward"] = {"fwd_site_updates_per_s": g["ticks"] / g["fwd"],
                             "overhead": g["overhead"], "replicas": g["replicas"],
                             "sweeps": g["sweeps"],
