@@ -1,0 +1,87 @@
+"""Degenerate and boundary cases of the method on the GPU (needs an MI355X).
+
+Each case runs through the C-ABI in the phase-by-phase form and in the
+persistent forms (multi-slot where the domains allow it, and forced
+one-domain-per-wavefront), and must match the oracle bit for bit:
+
+* rates that round to 0 (T -> 0: uphill flips never happen) and rates at or
+  next to 2^32 (T -> infinity: hardly any null ticks), Barker's w = 1/2;
+* J = 0 (independent spins in a field), J < 0 (antiferromagnet), a field
+  that dominates the coupling;
+* N_I = 1 (one tick per visit) and N_I far above the domain size and not a
+  multiple of the 64-tick batch;
+* the smallest checkerboard (2 x 2 domains of 4 x 4), 64 x 64 domains
+  (64-bit rows), and a 12 x 12 domain (the slot draw rejects 2^32 mod 144);
+* calls with no sweeps and calls with no record point.
+"""
+import numpy as np
+import pytest
+
+from paper_1403_4674_amd import kmc
+from tests.gpu_helpers import assert_records_equal, assert_replica_equal, oracle_for, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    return torch
+
+
+CASES = {
+    "frozen": dict(L=32, tile=8, T=0.05, h=0.0),
+    "hot": dict(L=32, tile=8, T=1.0e6, h=0.0),
+    "barker_hot": dict(L=24, tile=12, T=1.0e6, rate_model=kmc.RATE_BARKER),
+    "free_spins": dict(L=16, tile=8, J=0.0, h=0.3, T=1.0),
+    "antiferro": dict(L=32, tile=16, J=-1.0, h=0.0, T=1.5),
+    "strong_field": dict(L=32, tile=8, J=1.0, h=5.0, T=2.0),
+    "one_tick": dict(L=32, tile=8, T=2.3, steps_per_visit=1),
+    "long_visit": dict(L=16, tile=8, T=2.3, steps_per_visit=1000),
+    "smallest": dict(L=8, tile=4, T=2.0),
+    "tile64": dict(L=128, tile=64, T=2.6, h=-0.05),
+    "odd_domain": dict(L=48, tile=12, T=2.2, h=0.1),
+}
+FORMS = {"phased": 0,
+         "persistent_multi": kmc.F_PERSISTENT | kmc.F_MULTI,
+         "persistent_wave": kmc.F_PERSISTENT | kmc.F_NO_MULTI}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("case", list(CASES))
+def test_degenerate_case_matches_oracle(torch_cuda, oracle_lib, case, form):
+    d = CASES[case]
+    sweeps, every = 12, 4
+    say(f"edge case {case}, {form}")
+    lat = kmc.Lattice([d], 21)
+    lat.run(sweeps, every, FORMS[form])
+    rec = lat.records()
+    o = oracle_for(oracle_lib, d, 21, 0)
+    orec = o.run(sweeps, every)
+    assert_replica_equal(lat, 0, o, rec[0], orec, f"{case} {form}")
+    if case == "frozen":
+        # from a random start at T -> 0 only downhill and level flips occur
+        e = -rec[0]["B"]
+        assert (np.diff(e) <= 0).all()
+    if case == "hot":
+        assert rec[0]["events"][-1] > 0.99 * rec[0]["steps"][-1]
+    lat.close()
+
+
+def test_calls_without_sweeps_or_record_points(torch_cuda, oracle_lib):
+    d = dict(L=16, tile=8, T=2.4, h=0.2)
+    say("zero sweeps / no record point")
+    lat = kmc.Lattice([d], 5)
+    o = oracle_for(oracle_lib, d, 5, 0)
+    lat.run(0, 1)
+    assert lat.records().shape == (1, 0)
+    lat.run(3, 5)  # no record inside this call
+    assert len(o.run(3, 5)) == 0
+    assert lat.records().shape == (1, 0)
+    lat.run(10, 4, kmc.F_PERSISTENT)  # records after sweeps 7 and 11
+    orec = o.run(10, 4)
+    rec = lat.records()
+    assert list(rec[0]["sweep"]) == [7, 11]
+    assert_records_equal(rec[0], orec, "sparse records")
+    assert np.array_equal(lat.spins(0), o.spins())
