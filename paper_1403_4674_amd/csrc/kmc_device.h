@@ -561,15 +561,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     double R = rdl_f64(Pinc, 9);
     const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
 
-    double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
+    double w_lane = 0.0;  // score: w_c in the class lanes (the other tables at the end)
     if constexpr (SCORE) {
-        if (lane < 10) {
-            w_lane = rt->w[lane];
-            aJ_lane = rt->aJ[lane];
-            ah_lane = rt->ah[lane];
-            gJ_lane = rt->gJ[lane];
-            gh_lane = rt->gh[lane];
-        }
+        if (lane < 10) w_lane = rt->w[lane];
     }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
@@ -703,8 +697,11 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     if constexpr (SCORE) {
         if (m_null) null_run(m_null);
         const double ev = (double)ev_lane;
-        out.sJ = rowsum16_f64(gJ_lane * ev - aJ_lane * A_lane, lane);
-        out.sh = rowsum16_f64(gh_lane * ev - ah_lane * A_lane, lane);
+        const int cl = lane < 10 ? lane : 0;
+        const double gJ = lane < 10 ? rt->gJ[cl] : 0.0, gh = lane < 10 ? rt->gh[cl] : 0.0;
+        const double aJ = lane < 10 ? rt->aJ[cl] : 0.0, ah = lane < 10 ? rt->ah[cl] : 0.0;
+        out.sJ = rowsum16_f64(gJ * ev - aJ * A_lane, lane);
+        out.sh = rowsum16_f64(gh * ev - ah * A_lane, lane);
     }
     {
         // events, dM and dB from the per-class event counts: a flip of class

@@ -161,15 +161,9 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     const uint32_t vm_row = (1u << B) - 1u;
     const uint32_t upto_lane = (2u << sl) - 1u;  // bits 0..sl
 
-    double w_lane = 0.0, aJ_lane = 0.0, ah_lane = 0.0, gJ_lane = 0.0, gh_lane = 0.0;
+    double w_lane = 0.0;  // score: w_c in the class lanes (the other tables at the end)
     if constexpr (SCORE) {
-        if (A.on && sl < 10) {
-            w_lane = rt->w[sl];
-            aJ_lane = rt->aJ[sl];
-            ah_lane = rt->ah[sl];
-            gJ_lane = rt->gJ[sl];
-            gh_lane = rt->gh[sl];
-        }
+        if (A.on && sl < 10) w_lane = rt->w[sl];
     }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
@@ -286,8 +280,12 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     if constexpr (SCORE) {
         null_run(m_null, A.on);
         const double ev = (double)ev_lane;
-        out.sJ = sum_row_f64(gJ_lane * ev - aJ_lane * A_lane, base);
-        out.sh = sum_row_f64(gh_lane * ev - ah_lane * A_lane, base);
+        const bool cl_on = A.on && sl < 10;
+        const int cl = cl_on ? sl : 0;
+        const double gJ = cl_on ? rt->gJ[cl] : 0.0, gh = cl_on ? rt->gh[cl] : 0.0;
+        const double aJ = cl_on ? rt->aJ[cl] : 0.0, ah = cl_on ? rt->ah[cl] : 0.0;
+        out.sJ = sum_row_f64(gJ * ev - aJ * A_lane, base);
+        out.sh = sum_row_f64(gh * ev - ah * A_lane, base);
     }
     // events, dM and dB of each slot from its per-class event counts
 #pragma unroll
@@ -498,11 +496,13 @@ __device__ void run_item(const KParams &K, const MItem &it, int wave, int lane, 
 
 // Multi-slot persistent kernel: workgroup items (teams of four wavefronts)
 // first, then wavefront items; every wavefront leaves once both queues are
-// drained.  Both instantiations are held to 168 registers (three wavefronts
-// per SIMD): no spills for the forward one; the score one spills 96 bytes
-// per lane and still runs 20% faster than at two wavefronts per SIMD.
+// drained.  Occupancy: the forward instantiation is held to 168 registers
+// (three wavefronts per SIMD, no spills); the score one to 128 (four per
+// SIMD: it spills a few bytes outside the event loop and runs ~9% faster
+// than at three on the differentiable batch, while the forward one at four
+// loses ~13% on the ragged batch).
 template <bool SCORE>
-__global__ __launch_bounds__(64 * kWavesPerPersistentGroup) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_persistent_multi(
+__global__ __launch_bounds__(64 * kWavesPerPersistentGroup) __attribute__((amdgpu_waves_per_eu(SCORE ? 4 : 3, 8))) void k_persistent_multi(
     KParams K, const MItem *__restrict__ items, int n_wg_items, int n_wave_items,
     int64_t n_sweeps) {
     const int64_t sweep0 = K.ctl->sweep;  // device counters: replayable launch
