@@ -23,24 +23,29 @@ def valid_tiles(L, max_tile=32, min_tile=8):
             if L % B == 0 and (L // B) % 2 == 0]
 
 
-def _rate(descs, seed, sweeps):
+def _rate(descs, seed, sweeps, warmup=4, repeats=2):
+    """Site-updates/s of the persistent kernel on the batch: `warmup` sweeps
+    first (the random start relaxes fastest and has the most events), then
+    the best of `repeats` timed runs of `sweeps` sweeps."""
     import torch
     stream = torch.cuda.current_stream()
     lat = kmc.Lattice(descs, seed)
-    lat.run(1, 1, kmc.F_PERSISTENT)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
-    b.record(stream)
-    torch.cuda.synchronize()
-    sec = a.elapsed_time(b) / 1e3
+    lat.run(warmup, warmup, kmc.F_PERSISTENT)
+    best = 0.0
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
+        b.record(stream)
+        torch.cuda.synchronize()
+        best = max(best, sweeps * sum(d["L"] ** 2 for d in descs) / (a.elapsed_time(b) / 1e3))
     lat.close()
-    return sweeps * sum(d["L"] ** 2 for d in descs) / sec
+    return best
 
 
-def tune_batch(name, descs, seed, sweeps=8, max_tile=32, passes=1, path=DEFAULT_PATH,
+def tune_batch(name, descs, seed, sweeps=30, max_tile=32, passes=1, path=DEFAULT_PATH,
                verbose=False, starts=None):
     """Chooses a tile per lattice side for the batch `descs` (dicts with L,
     tile, ...), records the choice under `name` and returns {L: tile}.
@@ -122,7 +127,7 @@ def main():
     from . import workloads
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
-    ap.add_argument("--sweeps", type=int, default=8)
+    ap.add_argument("--sweeps", type=int, default=30)
     args = ap.parse_args()
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
