@@ -2,15 +2,18 @@
 """Benchmark of the domain-decomposed sequential-update kMC hot path.
 
 One step = one schedule sweep of the 1024x1024 periodic Ising lattice cut
-into 32x32 domains (1024 domains, 4 colour phases of 256 concurrent domain
-processes, N_I = 1024 ticks per visit, Metropolis, T = 2.269, random start):
-every domain visit, class bookkeeping, event selection, clock and the sweep
-record.  value = site updates (ticks, null ticks included) per second.
+into 32x32 domains (1024 domains, 4 colour phases of 256 domains each,
+N_I = 1024 ticks per visit, Metropolis, T = 2.269, random start): every
+domain visit, class bookkeeping, event selection, clock and the sweep
+record.  value = site updates (ticks, null ticks included) per second, with
+the sweep run as one dataflow launch (each visit starts once the visits of
+its neighbours that precede it in the schedule are done; KMC_F_FLOW).
 
-Extra measurements on the same line: the batched persistent form
-(4096 ragged replicas), the backward score replay overhead (1024 replicas of
-64x64), the roofline of the dominant kernel and the serial CPU oracle on a
-bounded sample of the same workload.
+Extra measurements on the same line: the same workload as four phase
+launches per sweep, the batched persistent form (4096 ragged replicas), the
+backward score replay and fused score (1024 replicas of 64x64), the
+roofline of the dominant kernel and the serial CPU oracle on a bounded
+sample of the same workload.
 """
 import argparse
 import json
@@ -38,17 +41,21 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
+    "kernel": "k_phase<uint32_t,false>",
     "kernel_source_sha256": "ce411f87dd45cadd6595320ced74a0f1d60b91ff223b9ac610adc2f61193a7b8",
     "fetch_kib": 911.5, "fetch_scale": 1048576.0 / 524308.19,
     "write_kib": 288.0, "write_scale": 1048576.0 / 1048576.0,
 }
-# algorithmic bytes per plain launch: each of the 256 domains reads its
-# 32x32 int8 tile and 4 x 32 halo sites and writes the tile back
-PLAIN_ALG_BYTES = 256 * (2 * 32 * 32 + 4 * 32)
+# algorithmic bytes per colour phase of the plain workload: each of the 256
+# domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the
+# tile back (a one-launch sweep covers four phases)
+PLAIN_ALG_BYTES_PER_PHASE = 256 * (2 * 32 * 32 + 4 * 32)
 
 
-def plain_traffic():
+def plain_traffic(kernel):
     import hashlib
+    if kernel != PLAIN_TRAFFIC["kernel"]:
+        return None
     src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", "kmc_device.h")
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != PLAIN_TRAFFIC["kernel_source_sha256"]:
@@ -69,29 +76,34 @@ def timed(fn, stream):
     return a.elapsed_time(b) / 1e3
 
 
-def plain(args, kmc, workloads):
+def plain(args, kmc, workloads, phased=False, steps=None):
+    """The 1024^2 lattice, one sweep per step.  Default form: one dataflow
+    launch per sweep (KMC_F_FLOW); phased: four colour-phase launches."""
     import torch
+    steps = args.steps if steps is None else steps
     seed, descs, _ = workloads.single_1024(2.269)
     d = descs[0]
     lat = kmc.Lattice(descs, seed)
     stream = torch.cuda.current_stream()
     # without a graph, HIP events on the context stream bracket every launch
-    # of the phase kernel inside the timed region (KMC_F_TIMING)
-    flags = kmc.F_GRAPH if args.graph else kmc.F_TIMING
+    # of the hot kernel inside the timed region (KMC_F_TIMING)
+    flags = (kmc.F_GRAPH if args.graph else kmc.F_TIMING) | (0 if phased else kmc.F_FLOW)
     lat.run(args.warmup, 1, flags)
     torch.cuda.synchronize()
     if not args.graph:
         lat.timing()
     ev0 = lat.records()[0][-1]["events"] if args.warmup else 0
-    sec = timed(lambda: lat.run(args.steps, 1, flags), stream)
-    kernel_ms, launches = lat.timing() if not args.graph else (None, 4 * args.steps)
+    sec = timed(lambda: lat.run(steps, 1, flags), stream)
+    kernel_ms, launches = (lat.timing() if not args.graph
+                           else (None, (4 if phased else 1) * steps))
     rec = lat.records()[0]
     events = int(rec[-1]["events"] - ev0)
-    ticks = args.steps * d["L"] ** 2
+    ticks = steps * d["L"] ** 2
     lat.close()
     return dict(sec=sec, ticks=ticks, events=events, launches=launches,
                 kernel_sec=None if kernel_ms is None else kernel_ms / 1e3,
-                desc=d, seed=seed)
+                desc=d, seed=seed, phased=phased,
+                kernel="k_phase<uint32_t,false>" if phased else "k_flow<uint32_t,false>")
 
 
 def parse_tiles(text):
@@ -197,6 +209,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--graph", action="store_true", help="replay sweeps from a hipGraph")
+    ap.add_argument("--phased", action="store_true",
+                    help="plain form as four phase launches per sweep (default: one "
+                         "dataflow launch per sweep, KMC_F_FLOW)")
     ap.add_argument("--batched-sweeps", type=int, default=40)
     ap.add_argument("--grad-sweeps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -237,7 +252,7 @@ def main():
         print(json.dumps({"backward": g}), flush=True)
         return
 
-    p = plain(args, kmc, workloads)
+    p = plain(args, kmc, workloads, phased=args.phased)
     value = p["ticks"] / p["sec"]
     # average duration of one phase-kernel launch: from the HIP events around
     # each launch; with --graph, the timed region over the launch count
@@ -262,18 +277,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain",
                    "L": d["L"], "tile": d["tile"], "steps_per_visit": d["steps_per_visit"],
-                   "T": d["T"], "seed": p["seed"], "graph": bool(args.graph)},
+                   "T": d["T"], "seed": p["seed"], "graph": bool(args.graph),
+                   "form": "phase_launches" if p["phased"] else "one_dataflow_launch_per_sweep"},
         "events_per_s": p["events"] / p["sec"],
         "roofline": {
             "bound": "alu",
-            "kernel": "k_phase<uint32_t,false>",
+            "kernel": p["kernel"],
             "achieved": achieved / 1e12,
             "peak": ALU_PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / ALU_PEAK_LANE_OPS,
-            "traffic": plain_traffic(),
+            "traffic": plain_traffic(p["kernel"]),
             "traffic_unit": "B/launch",
-            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES,
+            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES_PER_PHASE * (1 if p["phased"] else 4),
             "per_launch_ms": per_launch * 1e3,
             "launches": p["launches"],
             "ops_per_launch": ops / p["launches"],
@@ -282,12 +298,21 @@ def main():
         },
     }
     if args.mode == "all":
+        if not args.phased:  # the four-launches-per-sweep form of the same workload
+            q = plain(args, kmc, workloads, phased=True, steps=max(args.steps // 2, 1))
+            line["plain_phased"] = {"value": q["ticks"] / q["sec"], "unit": "site-updates/s",
+                                    "steps": max(args.steps // 2, 1),
+                                    "kernel": q["kernel"],
+                                    "per_launch_ms": q["kernel_sec"] * 1e3 / q["launches"],
+                                    "flow_speedup": value / (q["ticks"] / q["sec"])}
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
         b_ops = OPS_PER_TICK * b["ticks"] + OPS_PER_EVENT * b["events"]
         line["batched"] = {"value": b["ticks"] / b["sec"], "unit": "site-updates/s",
                            "replicas": b["replicas"], "sweeps": b["sweeps"],
                            "vs_plain": (b["ticks"] / b["sec"]) / value,
+                           "vs_plain_phased": (b["ticks"] / b["sec"])
+                           / line.get("plain_phased", {"value": value})["value"],
                            "roofline": {"bound": "alu", "kernel": "k_persistent_multi<false>",
                                         "achieved": b_ops / b["kernel_sec"] / 1e12,
                                         "peak": ALU_PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
@@ -301,7 +326,9 @@ def main():
                             / value,
                             "fused_overhead": g["fused_overhead"],
                             "fused_site_updates_per_s": g["ticks"] / g["fused"],
-                            "fused_vs_plain": (g["ticks"] / g["fused"]) / value}
+                            "fused_vs_plain": (g["ticks"] / g["fused"]) / value,
+                            "fused_vs_plain_phased": (g["ticks"] / g["fused"])
+                            / line.get("plain_phased", {"value": value})["value"]}
         line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

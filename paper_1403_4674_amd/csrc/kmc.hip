@@ -78,6 +78,9 @@ struct kmc_ctx {
     RepAcc *d_acc = nullptr;
     Record *d_rec = nullptr;
     Ctl *d_ctl = nullptr;
+    int64_t *d_done = nullptr;  // per-domain visit counters of the one-launch sweep
+    bool graph_flow = false;    // the cached phase graph was captured with flow
+    bool flow = false;          // phase-by-phase sweeps as one dataflow launch
     int32_t *d_task_rep = nullptr;
     int32_t *d_order = nullptr;
     int64_t rec_cap = 0, n_rec = 0;
@@ -289,6 +292,29 @@ void timed_launch(kmc_ctx *c, F fn) {
 
 template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K) {
+    if (c->flow) {
+        // the whole sweep in one launch per row-mask width (replicas of the
+        // two widths never interact)
+        timed_launch(c, [&] {
+            if (c->n_tasks32) {
+                K.task_begin = 0;
+                hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE>),
+                                   dim3(c->n_phase * c->n_tasks32), dim3(64), 0, c->stream, K,
+                                   c->n_tasks32, c->d_done);
+            }
+            if (c->n_tasks > c->n_tasks32) {
+                const int nt = c->n_tasks - c->n_tasks32;
+                K.task_begin = c->n_tasks32;
+                hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE>), dim3(c->n_phase * nt),
+                                   dim3(64), 0, c->stream, K, nt, c->d_done);
+            }
+        });
+        hipLaunchKernelGGL(kmcdev::k_sweep_end, dim3(c->n_rep), dim3(64), 0, c->stream, K);
+        hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl,
+                           (int64_t)1);
+        launch_check(c, "sweep launch");
+        return;
+    }
     for (int p = 0; p < c->n_phase; ++p) {
         timed_launch(c, [&] {
         if (c->n_tasks32) {
@@ -393,7 +419,12 @@ void run_graph(kmc_ctx *c, int64_t n_sweeps) {
     }
     hipStream_t gs = c->stream ? c->stream : c->graph_stream;
     hipStream_t saved = c->stream;
+    if (c->graph && c->graph_flow != c->flow) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
     if (!c->graph) {
+        c->graph_flow = c->flow;
         hipGraph_t g;
         c->stream = gs;
         hip_check(c, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal),
@@ -449,6 +480,14 @@ void run_persistent_graph(kmc_ctx *c, KParams K, int64_t n_sweeps, int32_t recor
 
 int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * d.L; }
 
+// A one-launch sweep whose bounded wait gave up leaves ctl->err set (a
+// dependency never satisfied): the results of the run are not valid.
+void check_flow_error(kmc_ctx *c) {
+    Ctl h;
+    hip_check(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl copy");
+    if (h.err) fail(c, KMC_EDEVICE, "a one-launch sweep timed out waiting for a neighbour");
+}
+
 void destroy_buffers(kmc_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -457,7 +496,8 @@ void destroy_buffers(kmc_ctx *c) {
     void *bufs[] = {c->d_reps,  c->d_rates, c->d_spins, c->d_dom,   c->d_acc,
                     c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
                     c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
-                    c->r_ctl,   c->d_bins,  c->d_tmp_rec, c->d_order_nm, c->d_items};
+                    c->r_ctl,   c->d_bins,  c->d_tmp_rec, c->d_order_nm, c->d_items,
+                    c->d_done};
     for (void *p : bufs) dev_free(c, p);
 }
 
@@ -642,6 +682,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         c->d_dom = alloc_n<Dom>(c, dom);
         c->d_acc = alloc_n<RepAcc>(c, n_rep);
         c->d_ctl = alloc_n<Ctl>(c, 1);
+        c->d_done = alloc_n<int64_t>(c, std::max(dom, 1));
         c->d_task_rep = alloc_n<int32_t>(c, c->n_tasks);
         c->d_order = alloc_n<int32_t>(c, n_rep);
         c->d_order_nm = alloc_n<int32_t>(c, n_rep);
@@ -665,6 +706,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         hip_check(c, hipMemsetAsync(c->d_dom, 0, sizeof(Dom) * std::max(dom, 1), s), "zero");
         hip_check(c, hipMemsetAsync(c->d_acc, 0, sizeof(RepAcc) * n_rep, s), "zero");
         hip_check(c, hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s), "zero");
+        hip_check(c, hipMemsetAsync(c->d_done, 0, sizeof(int64_t) * std::max(dom, 1), s),
+                  "zero");
         if (any_given) {
             int64_t src = 0;
             for (int rho = 0; rho < n_rep; ++rho) {
@@ -717,6 +760,8 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             fail(c, KMC_EINVAL, "KMC_F_SCORE is not available with KMC_F_GRAPH");
         if ((flags & KMC_F_TIMING) && (flags & KMC_F_GRAPH))
             fail(c, KMC_EINVAL, "KMC_F_TIMING is not available with KMC_F_GRAPH");
+        if ((flags & KMC_F_FLOW) && (flags & KMC_F_PERSISTENT))
+            fail(c, KMC_EINVAL, "KMC_F_FLOW applies to the phase-by-phase form only");
         if (n_sweeps == 0) return KMC_OK;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
@@ -738,6 +783,11 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             c->ck_flags = flags;
         }
         c->timing = (flags & KMC_F_TIMING) != 0;
+        c->flow = (flags & KMC_F_FLOW) != 0;
+        if (c->flow)  // counters restart with every run (a replay may go back in sweeps)
+            hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((c->n_dom + 255) / 256)),
+                               dim3(256), 0, c->stream, c->d_done, (int64_t)c->n_dom,
+                               (int64_t)0);
         KParams K = params(c);
         const bool score = (flags & KMC_F_SCORE) != 0;
         if (score || (flags & KMC_F_CHECKPOINT)) c->fused_score = false;
@@ -804,6 +854,7 @@ extern "C" kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capac
         hip_check(c, hipMemcpyAsync(h.data(), c->d_rec, sizeof(Record) * h.size(),
                                     hipMemcpyDeviceToHost, c->stream), "record copy");
         hip_check(c, hipStreamSynchronize(c->stream), "record sync");
+        check_flow_error(c);
         for (int rho = 0; rho < c->n_rep; ++rho)
             for (int64_t k = 0; k < n; ++k)
                 std::memcpy(&out[rho * capacity + k], &h[k * c->n_rep + rho], sizeof(Record));
@@ -864,10 +915,15 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         K.write_records = 0;
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
-        if (c->ck_flags & KMC_F_PERSISTENT)
+        if (c->ck_flags & KMC_F_PERSISTENT) {
             launch_persistent<true>(c, K, c->ck_n_sweeps, c->ck_flags);
-        else
+        } else {
+            c->flow = (c->ck_flags & KMC_F_FLOW) != 0;
+            if (c->flow)
+                hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((c->n_dom + 255) / 256)),
+                                   dim3(256), 0, s, c->d_done, (int64_t)c->n_dom, (int64_t)0);
             for (int64_t i = 0; i < c->ck_n_sweeps; ++i) launch_sweep<true>(c, K);
+        }
         hip_check(c, hipMemcpy2DAsync(score, (size_t)capacity * 2 * sizeof(double), c->d_bins,
                                       (size_t)n_bins * 2 * sizeof(double),
                                       (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind, s),

@@ -87,7 +87,8 @@ struct Ctl {
     int64_t rec_every;  // record interval of the current run
     int64_t queue;      // persistent team-queue head
     int64_t queue2;     // persistent solo-queue head
-    int64_t pad[2];
+    int64_t err;        // nonzero: a bounded wait of k_flow gave up
+    int64_t pad;
 };
 
 struct KParams {
@@ -803,6 +804,102 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
 }
 
 // End of a sweep: one wavefront per replica writes the record when due.
+// Number of visits of colour `col` at positions before p in the sweep's
+// schedule (random order: one visit per sweep, at the position held in the
+// 2-bit field col of pos_of; palindrome ABCDDCBA: two).
+__device__ inline int visits_before(const Rep &rp, uint32_t pos_of, int col, int p) {
+    if (rp.sched == 1) return (col < p ? 1 : 0) + (7 - col < p ? 1 : 0);
+    return (int)((pos_of >> (2 * col)) & 3u) < p ? 1 : 0;
+}
+
+constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;
+
+// One whole sweep of the phase-by-phase form in one launch.  Block b runs
+// phase p = b / n_tasks of task b % n_tasks, once every visit of a
+// neighbouring domain (and, in the palindrome, of the domain itself) that
+// precedes it in the sweep's sequential order has finished.  Each domain
+// publishes 4 w + (its visits so far in sweep w) with a device-scope
+// release after writing its tile back; waiters read it with a device-scope
+// acquire.  The halo every visit reads is therefore exactly the one of the
+// sequential order, so the results equal the phase-by-phase launches bit
+// for bit, while domains of non-adjacent colours, and domains whose
+// neighbours finished early, run ahead instead of waiting for a whole
+// phase.  Blocks are numbered phase-major, so a block only waits on blocks
+// numbered before it.  A wait that exceeds kFlowMaxPolls polls sets ctl->err
+// and gives up (the host reports the run as failed), so no wave can hang.
+template <typename MT, bool SCORE>
+__global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *done) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
+    const int p = (int)blockIdx.x / n_tasks;
+    const int task = K.task_begin + (int)blockIdx.x % n_tasks;
+    const int rho = K.task_rep[task];
+    const Rep rp = K.reps[rho];
+    const uint32_t w = (uint32_t)K.ctl->sweep;
+    int vis;
+    const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
+    if (col < 0) return;
+    int d, oy, ox;
+    colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
+    int64_t *dn = done + rp.dom_off;
+    const int64_t base = 4 * (int64_t)w;
+    if (__lane_id() == 0) {
+        uint32_t pos_of = 0;  // 2-bit position of each colour in this sweep's order
+        if (rp.sched != 1) {
+            const int idx = schedule_index(K.seed, (uint32_t)rho, w);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pos_of |= (uint32_t)q << (2 * perm_element(idx, q));
+        }
+        const int NT = rp.NT, ty = d / NT, tx = d - ty * NT;
+        auto wait_for = [&](int ey, int ex) {
+            const int need = visits_before(rp, pos_of, 2 * (ey & 1) + (ex & 1), p);
+            if (need == 0) return;
+            const int64_t *cnt = dn + ey * NT + ex;
+            int64_t polls = 0;
+            while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                   base + need) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++polls > kFlowMaxPolls) {
+                    __hip_atomic_store(&K.ctl->err, (int64_t)1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    return;
+                }
+            }
+        };
+        wait_for((ty + NT - 1) % NT, tx);
+        wait_for((ty + 1) % NT, tx);
+        wait_for(ty, (tx + NT - 1) % NT);
+        wait_for(ty, (tx + 1) % NT);
+        wait_for(ty, tx);  // the palindrome's second visit waits for the first
+    }
+    __builtin_amdgcn_wave_barrier();
+    const VisitOut o = visit_domain<MT, SCORE>(
+        K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
+        (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+    if (__lane_id() == 0) {
+        if (o.events) {
+            atomicAdd((unsigned long long *)&K.acc[rho].M, (unsigned long long)o.dM);
+            atomicAdd((unsigned long long *)&K.acc[rho].B, (unsigned long long)o.dB);
+            atomicAdd((unsigned long long *)&K.acc[rho].events,
+                      (unsigned long long)o.events);
+        }
+        if constexpr (SCORE) {
+            const int64_t bin = K.ctl->run_done / K.ctl->rec_every;
+            double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
+            atomicAdd(b, o.sJ);
+            atomicAdd(b + 1, o.sh);
+        }
+        // this domain's visits so far in sweep w (the palindrome's second
+        // visit has vis = 1)
+        __hip_atomic_store(dn + d, base + (int64_t)vis + 1,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ __launch_bounds__(64) void k_sweep_end(KParams K) {
     const int rho = blockIdx.x;
     const Ctl c = *K.ctl;

@@ -216,3 +216,72 @@ def test_timing_instrumentation_changes_nothing(torch_cuda):
     assert n >= 1 and ms > 0.0
     assert np.array_equal(a.records(), b.records())
     assert np.array_equal(a.spins(0), b.spins(0))
+
+
+FLOW_MIX = [dict(L=16, tile=8, T=2.5, steps_per_visit=64),
+            dict(L=24, tile=12, T=1.9, h=0.2),
+            dict(L=32, tile=8, T=3.1, h=-0.1, steps_per_visit=10),
+            dict(L=64, tile=16, T=2.2, h=0.05, schedule=kmc.SCHED_PALINDROME),
+            dict(L=128, tile=64, T=2.6, steps_per_visit=700),
+            dict(L=48, tile=24, T=1.6, h=0.4),
+            dict(L=8, tile=4, T=2.0, schedule=kmc.SCHED_PALINDROME)]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_one_launch_sweeps_are_bit_identical(torch_cuda, oracle_lib, graph):
+    """KMC_F_FLOW (one launch per sweep, visits ordered by per-domain
+    counters) against the phase launches and the oracle: both row widths,
+    the palindrome, odd domains, 2x2 domains."""
+    say(f"one-launch sweeps, graph={graph}")
+    a = kmc.Lattice(FLOW_MIX, 44)
+    b = kmc.Lattice(FLOW_MIX, 44)
+    a.run(21, 3)
+    b.run(21, 3, kmc.F_FLOW | (kmc.F_GRAPH if graph else 0))
+    b.run(19, 1, kmc.F_FLOW | (kmc.F_GRAPH if graph else 0))  # a second run: counters restart
+    a.run(19, 1)
+    ra, rb = a.records(), b.records()
+    assert np.array_equal(ra, rb)
+    for rho in range(len(FLOW_MIX)):
+        assert np.array_equal(a.spins(rho), b.spins(rho)), rho
+        assert np.array_equal(a.domain_state(rho)[2], b.domain_state(rho)[2])
+    for rho in (0, 3, 4, 6):
+        o = oracle_for(oracle_lib, FLOW_MIX[rho], 44, rho)
+        orec = np.concatenate([o.run(21, 3), o.run(19, 1)])
+        assert_replica_equal(b, rho, o, rb[rho], orec, f"flow replica {rho}")
+
+
+@pytest.mark.parametrize("which", ["1024", "4096"])
+def test_one_launch_sweeps_full_shapes(torch_cuda, oracle_lib, which):
+    if which == "1024":
+        seed, descs, _ = workloads.single_1024(2.269)
+        sweeps = 3
+    else:
+        seed, descs, _ = workloads.quench_4096()
+        descs = [dict(descs[0], steps_per_visit=256)]
+        sweeps = 2
+    say(f"one-launch sweeps on {which}^2, {sweeps} sweeps")
+    lat, g, oras, o = run_both(oracle_lib, descs, seed, sweeps, 1, kmc.F_FLOW | kmc.F_TIMING)
+    ms, n = lat.timing()
+    assert n == sweeps and ms > 0
+    assert_replica_equal(lat, 0, oras[0], g[0], o[0], f"flow {which}")
+
+
+def test_one_launch_score_replay(torch_cuda, oracle_lib):
+    descs = FLOW_MIX[:4]
+    say("one-launch sweeps: score replay")
+    lat = kmc.Lattice(descs, 8)
+    lat.run(12, 4, kmc.F_FLOW | kmc.F_CHECKPOINT)
+    sc = lat.score(3)
+    for rho, d in enumerate(descs):
+        o = oracle_for(oracle_lib, d, 8, rho)
+        orec, osc = o.run(12, 4, score=True)
+        assert_records_equal(lat.records()[rho], orec, f"flow score replica {rho}")
+        ticks = 4 * d["L"] ** 2 * (2 if d.get("schedule") else 1)
+        np.testing.assert_allclose(sc[rho], osc, rtol=1e-10, atol=1e-11 * ticks)
+
+
+def test_one_launch_rejects_persistent(torch_cuda):
+    lat = kmc.Lattice([dict(L=16, tile=8, T=2.0)], 1)
+    with pytest.raises(kmc.KmcError) as e:
+        lat.run(2, 1, kmc.F_FLOW | kmc.F_PERSISTENT)
+    assert e.value.status == kmc.KMC_EINVAL
