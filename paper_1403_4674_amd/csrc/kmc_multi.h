@@ -56,8 +56,25 @@ __device__ __forceinline__ uint32_t scan_row(uint32_t v) {
     return v;
 }
 
+// Lane N of each 16-lane row copied to the whole row (DPP row_newbcast, a
+// VALU operand modifier: no LDS round trip).
+constexpr int kRowNewBcast = 0x150;
+
+template <int N>
+__device__ __forceinline__ uint32_t rowbcast(uint32_t v) {
+    return dpp<kRowNewBcast + N>(v);
+}
+
+template <int N>
+__device__ __forceinline__ double rowbcast_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = rowbcast<N>((uint32_t)b), hi = rowbcast<N>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double sum_row_f64(double v, int base) {
-    return sbc_f64(scan16_f64(v), base + 15);
+    (void)base;
+    return rowbcast_f64<15>(scan16_f64(v));
 }
 
 constexpr int kRowShl1 = 0x101;  // lane i <- lane i+1 inside a row
@@ -147,7 +164,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     for (int c = 0; c < 10; c += 2) {
         const uint32_t a = popc(class_mask<uint32_t>(c, S, P, VM));
         const uint32_t b = popc(class_mask<uint32_t>(c + 1, S, P, VM));
-        const uint32_t tot = sbc32(scan_row(a | (b << 16)), base + 15);
+        const uint32_t tot = rowbcast<15>(scan_row(a | (b << 16)));
         if (sl == c) n_lane = tot & 0xFFFFu;
         if (sl == c + 1) n_lane = tot >> 16;
     }
@@ -157,7 +174,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     const uint32_t sl3 = sl < 10 ? 3u * (uint32_t)sl : 30u;  // tally field (30: always 0)
     double W = (double)n_lane * rd_lane;
     double Pinc = scan16_f64(W);
-    double R = sbc_f64(Pinc, base + 9);
+    double R = rowbcast_f64<9>(Pinc);
     const uint32_t vm_row = (1u << B) - 1u;
     const uint32_t upto_lane = (2u << sl) - 1u;  // bits 0..sl
 
@@ -263,7 +280,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             }
             W = (double)n_lane * rd_lane;
             Pinc = scan16_f64(W);
-            R = sbc_f64(Pinc, base + 9);
+            R = rowbcast_f64<9>(Pinc);
 
             const uint32_t bx = 1u << xs;
             const uint32_t mrow = ((bx << 1) | (bx >> 1)) & vm_row;
