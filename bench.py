@@ -35,16 +35,17 @@ OPS_PER_EVENT = 64
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer lane-operations/s
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# HBM bytes of one phase-kernel launch of the plain workload: rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
+# HBM bytes of one launch of each plain-form kernel: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
 # counter reads for a 1 GiB device copy (profiles/copy_calibration_1GiB.md,
+# profiles/k_flow_ising2d_L1024_tile32_plain.md,
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
-    "kernel": "k_phase<uint32_t,false>",
-    "kernel_source_sha256": "ce411f87dd45cadd6595320ced74a0f1d60b91ff223b9ac610adc2f61193a7b8",
-    "fetch_kib": 911.5, "fetch_scale": 1048576.0 / 524308.19,
-    "write_kib": 288.0, "write_scale": 1048576.0 / 1048576.0,
+    "kernel_source_sha256": "a6537e98c88f3faa81869d71d945dede29c7e371ec79aa1e662e7c3604f7340b",
+    "fetch_scale": 1048576.0 / 524308.19, "write_scale": 1048576.0 / 1048576.0,
+    "kib": {"k_flow<uint32_t,false>": (3491.48, 1184.13),
+            "k_phase<uint32_t,false>": (914.01, 288.0)},
 }
 # algorithmic bytes per colour phase of the plain workload: each of the 256
 # domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the
@@ -54,14 +55,15 @@ PLAIN_ALG_BYTES_PER_PHASE = 256 * (2 * 32 * 32 + 4 * 32)
 
 def plain_traffic(kernel):
     import hashlib
-    if kernel != PLAIN_TRAFFIC["kernel"]:
+    t = PLAIN_TRAFFIC
+    if kernel not in t["kib"]:
         return None
     src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", "kmc_device.h")
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != PLAIN_TRAFFIC["kernel_source_sha256"]:
+        if hashlib.sha256(f.read()).hexdigest() != t["kernel_source_sha256"]:
             return None
-    t = PLAIN_TRAFFIC
-    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+    fetch, write = t["kib"][kernel]
+    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
 
 
 def timed(fn, stream):
