@@ -90,10 +90,12 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
 
-/* One replica.  Domain side `tile` = B: L % B == 0, B % 4 == 0, 4 <= B <= 64
- * and L/B even (a 4-colour checkerboard; the paper's Fig. 1 partition with
- * N_D = (L/B)^2).  steps_per_visit = N_I ticks per domain process
- * (Sec. 2.2); 0 selects B*B (one Monte Carlo step per site per visit). */
+/* One replica.  Domain side `tile` = B: L % B == 0, 1 <= B <= 64 and L/B
+ * even (a 4-colour checkerboard; the paper's Fig. 1 partition with
+ * N_D = (L/B)^2), or L/B = 1 with B >= 3: the unpartitioned lattice as one
+ * periodic domain (N_D = 1, the paper's reference dynamics).
+ * steps_per_visit = N_I ticks per domain process (Sec. 2.2); 0 selects B*B
+ * (one Monte Carlo step per site per visit). */
 typedef struct {
     double J, h, T;            /* coupling, field, k_B T (> 0)              */
     int32_t L;                 /* lattice side                              */

@@ -231,9 +231,12 @@ void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     };
     if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
         bad("J, h must be finite and T > 0");
-    if (d.tile < 4 || d.tile > 64 || d.tile % 4) bad("tile must be a multiple of 4 in [4, 64]");
-    if (d.L < 2 * d.tile || d.L % d.tile) bad("L must be a multiple of tile, L >= 2 tile");
-    if ((d.L / d.tile) % 2) bad("L/tile must be even (4-colour checkerboard)");
+    if (d.tile < 1 || d.tile > 64) bad("tile must be in [1, 64]");
+    if (d.L < d.tile || d.L % d.tile) bad("L must be a multiple of tile");
+    if (d.L == d.tile && d.tile < 3)
+        bad("a lattice that is one domain needs tile >= 3 (four distinct neighbours)");
+    if (d.L > d.tile && (d.L / d.tile) % 2)
+        bad("L/tile must be 1 or even (4-colour checkerboard)");
     if ((int64_t)(d.L / d.tile) * (d.L / d.tile) > (1 << 20)) bad("more than 2^20 domains");
     if (d.steps_per_visit < 0) bad("steps_per_visit must be >= 0");
     if (d.rate_model != KMC_RATE_METROPOLIS && d.rate_model != KMC_RATE_BARKER)
@@ -583,7 +586,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 Rep &rp = c->reps[rho];
                 if ((rp.B > 32) != (pass == 1)) continue;
                 rp.task_off = (int32_t)task_rep.size();
-                for (int i = 0; i < rp.ND / 4; ++i) task_rep.push_back(rho);
+                for (int i = 0; i < std::max(rp.ND / 4, 1); ++i) task_rep.push_back(rho);
                 if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();
             }
         c->n_tasks = (int32_t)task_rep.size();
@@ -610,7 +613,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         };
         std::vector<int32_t> mrep;  // multi-slot candidates
         for (int rho = 0; rho < n_rep; ++rho)
-            if (c->reps[rho].B <= 16) mrep.push_back(rho);
+            if (c->reps[rho].B <= 16 && c->reps[rho].NT >= 2) mrep.push_back(rho);
         {
             std::stable_sort(mrep.begin(), mrep.end(), by_cost);
             std::vector<MItem> wg, wv;

@@ -504,21 +504,36 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     const int B4 = B >> 2;
     const uint32_t nd = rp.nd, thr = rp.thr;
 
-    // ---- stage the tile and the top/bottom halo rows through LDS
+    // ---- stage the tile and the top/bottom halo rows through LDS.  LDS rows
+    // are padded to whole dwords (stride SB); sides that are multiples of 4
+    // move as dwords, other sides byte by byte.
+    const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds;
     uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
-    for (int q = lane; q < B * B4; q += 64) {
-        const int row = q / B4, c4 = q - row * B4;
-        const uint32_t v = *reinterpret_cast<const uint32_t *>(
-            lat + (int64_t)(oy + row) * L + ox + 4 * c4);
-        *reinterpret_cast<uint32_t *>(tile + row * B + 4 * c4) = v;
-    }
-    if (lane < 2 * B4) {
-        const int which = lane / B4, c4 = lane - which * B4;
-        const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
-        const uint32_t v =
-            *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + ox + 4 * c4);
-        *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) = v;
+    if ((B & 3) == 0) {
+        for (int q = lane; q < B * B4; q += 64) {
+            const int row = q / B4, c4 = q - row * B4;
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(
+                lat + (int64_t)(oy + row) * L + ox + 4 * c4);
+            *reinterpret_cast<uint32_t *>(tile + row * SB + 4 * c4) = v;
+        }
+        if (lane < 2 * B4) {
+            const int which = lane / B4, c4 = lane - which * B4;
+            const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
+            const uint32_t v =
+                *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + ox + 4 * c4);
+            *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) = v;
+        }
+    } else {
+        for (int q = lane; q < B * B; q += 64) {
+            const int row = q / B, col = q - row * B;
+            tile[row * SB + col] = (uint8_t)lat[(int64_t)(oy + row) * L + ox + col];
+        }
+        for (int q = lane; q < 2 * B; q += 64) {
+            const int which = q / B, col = q - which * B;
+            const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
+            hrow[which * 64 + col] = (uint8_t)lat[(int64_t)y * L + ox + col];
+        }
     }
     MT hl = 0, hr = 0;
     if (lane < B) {
@@ -528,19 +543,22 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     }
     wave_sync_lds();
 
-    const MT VM = lane < B ? (B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1))
-                           : (MT)0;
+    const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
+    const MT VM = lane < B ? vm_row : (MT)0;
     MT S = 0, top = 0, bot = 0;
-    for (int q = 0; q < B4; ++q) {
+    for (int q = 0; q < SB4; ++q) {
         if (lane < B)
             S |= (MT)bytes_to_bits(
-                     *reinterpret_cast<const uint32_t *>(tile + lane * B + 4 * q))
+                     *reinterpret_cast<const uint32_t *>(tile + lane * SB + 4 * q))
                  << (4 * q);
         top |= (MT)bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 4 * q))
                << (4 * q);
         bot |= (MT)bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 64 + 4 * q))
                << (4 * q);
     }
+    S &= VM;  // padding bytes decode to set bits: clear them
+    top &= vm_row;
+    bot &= vm_row;
     Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
 
     // ---- class counts: per-row popcounts, two classes per 32-bit word
@@ -561,7 +579,6 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     double W = (double)n_lane * rd_lane;
     double Pinc = scan16_f64(W);
     double R = rdl_f64(Pinc, 9);
-    const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
 
     double w_lane = 0.0;  // score: w_c in the class lanes (the other tables at the end)
     if constexpr (SCORE) {
@@ -574,6 +591,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     uint32_t m_null = 0;                   // null ticks since the last event (score)
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
+    // a lattice that is one domain is periodic in itself: its boundary
+    // neighbours are its own sites and change during the visit
+    const int wrapB = rp.NT == 1 ? B : 0;
 
     // Score.  A run of m null ticks adds m d ln(1 - R_w/n_d)/d theta =
     // -m sum_c n_c a_c / (n_d - R_w) (a_c = w_c d ln w_c/d theta), linear in
@@ -658,19 +678,28 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             // packed 3-bit per-class tallies (10 classes in 30 bits): row ys
             // holds the sites at columns xs -/+ 1, rows ys -/+ 1 the site at
             // column xs; the three rows are summed into row ys by DPP
+            // neighbour rows and columns; outside the tile (-1 or B) they are
+            // halo and frozen, unless the lattice is one periodic domain
             const bool up = c >= 5;
             const int c_new = up ? c - 5 : c + 5;
+            const int ym = ys - 1 + (ys == 0 ? wrapB : 0), yp = ys + 1 - (ys == B - 1 ? wrapB : 0);
+            const int xm = xs - 1 + (xs == 0 ? wrapB : 0), xp = xs + 1 - (xs == B - 1 ? wrapB : 0);
             const bool on_row = lane == ys;
-            const bool adj = (lane == ys - 1 || lane == ys + 1) && lane < B;
+            const bool adj = (lane == ym || lane == yp) && lane < B;
             constexpr int NB = 8 * (int)sizeof(MT);
-            const int ca = on_row ? xs - 1 : xs;
-            const bool va = on_row ? xs > 0 : adj;
-            const bool vb = on_row && xs < B - 1;
+            const int ca = on_row ? xm : xs;
+            const bool va = on_row ? xm >= 0 : adj;
+            const bool vb = on_row && xp < B;
             const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
-            const uint32_t pb = class_pos3<MT>(S, P, (xs + 1) & (NB - 1));
+            const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
             uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
-            nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
-            const uint32_t nb_s = rdl32(nb, ys);
+            uint32_t nb_s;
+            if (wrapB == 0) {
+                nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
+                nb_s = rdl32(nb, ys);
+            } else {
+                nb_s = rdl32(nb, ys) + rdl32(nb, ym) + rdl32(nb, yp);
+            }
             // every neighbour moves one class up (flip to +1) or down: the
             // whole tally shifts by one field (no class leaves its spin's range)
             const uint32_t sub_s = nb_s + (1u << (3 * c));
@@ -684,7 +713,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
 
             // flip, and move the neighbours' up-counts on the bit planes
             const MT bx = (MT)1 << xs;
-            const MT mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+            const MT mrow = (xm >= 0 ? (MT)1 << xm : (MT)0) | (xp < B ? (MT)1 << xp : (MT)0);
             if (on_row) S ^= bx;
             planes_step<MT>(P, on_row ? mrow : (adj ? bx : (MT)0), !up);
             pos = e + 1;
@@ -733,23 +762,42 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
 
     // ---- write the tile back through LDS
     if (lane < B) {
-        for (int q = 0; q < B4; ++q)
-            *reinterpret_cast<uint32_t *>(tile + lane * B + 4 * q) =
+        for (int q = 0; q < SB4; ++q)
+            *reinterpret_cast<uint32_t *>(tile + lane * SB + 4 * q) =
                 bits_to_bytes((uint32_t)(S >> (4 * q)) & 0xFu);
     }
     wave_sync_lds();
-    for (int q = lane; q < B * B4; q += 64) {
-        const int row = q / B4, c4 = q - row * B4;
-        *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
-            *reinterpret_cast<const uint32_t *>(tile + row * B + 4 * c4);
+    if ((B & 3) == 0) {
+        for (int q = lane; q < B * B4; q += 64) {
+            const int row = q / B4, c4 = q - row * B4;
+            *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
+                *reinterpret_cast<const uint32_t *>(tile + row * SB + 4 * c4);
+        }
+    } else {
+        for (int q = lane; q < B * B; q += 64) {
+            const int row = q / B, col = q - row * B;
+            lat[(int64_t)(oy + row) * L + ox + col] = (int8_t)tile[row * SB + col];
+        }
     }
     wave_sync_lds();  // LDS reads of the write-back finish before reuse
     return out;
 }
 
+// Number of domains of colour `col`: N_D / 4, or, for a lattice that is a
+// single domain (N_D = 1, periodic in itself), 1 for colour 0 and 0 otherwise.
+__device__ __forceinline__ int domains_of_colour(const Rep &rp, int col) {
+    return rp.NT == 1 ? (col == 0 ? 1 : 0) : rp.ND >> 2;
+}
+
 // Origin of the i-th domain of colour `col` (ascending domain index).
 __device__ __forceinline__ void colour_domain(const Rep &rp, int col, int i,
                                               int *d, int *oy, int *ox) {
+    if (rp.NT == 1) {
+        *d = 0;
+        *oy = 0;
+        *ox = 0;
+        return;
+    }
     const int half = rp.NT >> 1;
     const int tx = 2 * (i % half) + (col & 1);
     const int ty = 2 * (i / half) + (col >> 1);
@@ -781,7 +829,7 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     const uint32_t w = (uint32_t)K.ctl->sweep;
     int vis;
     const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
-    if (col < 0) return;
+    if (col < 0 || task - rp.task_off >= domains_of_colour(rp, col)) return;
     int d, oy, ox;
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
     const VisitOut o = visit_domain<MT, SCORE>(
@@ -837,7 +885,7 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
     const uint32_t w = (uint32_t)K.ctl->sweep;
     int vis;
     const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
-    if (col < 0) return;
+    if (col < 0 || task - rp.task_off >= domains_of_colour(rp, col)) return;
     int d, oy, ox;
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
     int64_t *dn = done + rp.dom_off;
@@ -992,12 +1040,12 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
     int64_t dM = 0, dB = 0, ev = 0;
     double sJ = 0.0, sh = 0.0;
     const int nphase = rp.sched == 1 ? 8 : 4;
-    const int per_colour = rp.ND >> 2;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const uint32_t w = (uint32_t)(sweep0 + i);
         for (int p = 0; p < nphase; ++p) {
             int vis;
             const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
+            const int per_colour = domains_of_colour(rp, col);
             for (int i2 = wave; i2 < per_colour; i2 += nw) {
                 int d, oy, ox;
                 colour_domain(rp, col, i2, &d, &oy, &ox);

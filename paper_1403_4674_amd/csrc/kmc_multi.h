@@ -103,21 +103,35 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     int8_t *lat = spins + A.spin_off;
     const Rates *rt = rates + A.rho;
 
-    // ---- stage the slot's tile and halo rows through LDS
+    // ---- stage the slot's tile and halo rows through LDS (rows padded to
+    // whole dwords, stride SB; sides that are not multiples of 4 byte by byte)
+    const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds + slot * kSlotLds;
     uint8_t *hrow = tile + 16 * 16;  // [0, 16): top, [16, 32): bottom
     if (A.on) {
-        for (int q = sl; q < B * B4; q += kSlotW) {
-            const int row = q / B4, c4 = q - row * B4;
-            *reinterpret_cast<uint32_t *>(tile + row * B + 4 * c4) =
-                *reinterpret_cast<const uint32_t *>(lat + (int64_t)(A.oy + row) * L + A.ox +
-                                                    4 * c4);
-        }
-        if (sl < 2 * B4) {
-            const int which = sl / B4, c4 = sl - which * B4;
-            const int y = which ? (A.oy + B) % L : (A.oy - 1 + L) % L;
-            *reinterpret_cast<uint32_t *>(hrow + which * 16 + 4 * c4) =
-                *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + A.ox + 4 * c4);
+        if ((B & 3) == 0) {
+            for (int q = sl; q < B * B4; q += kSlotW) {
+                const int row = q / B4, c4 = q - row * B4;
+                *reinterpret_cast<uint32_t *>(tile + row * SB + 4 * c4) =
+                    *reinterpret_cast<const uint32_t *>(lat + (int64_t)(A.oy + row) * L +
+                                                        A.ox + 4 * c4);
+            }
+            if (sl < 2 * B4) {
+                const int which = sl / B4, c4 = sl - which * B4;
+                const int y = which ? (A.oy + B) % L : (A.oy - 1 + L) % L;
+                *reinterpret_cast<uint32_t *>(hrow + which * 16 + 4 * c4) =
+                    *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + A.ox + 4 * c4);
+            }
+        } else {
+            for (int q = sl; q < B * B; q += kSlotW) {
+                const int row = q / B, col = q - row * B;
+                tile[row * SB + col] = (uint8_t)lat[(int64_t)(A.oy + row) * L + A.ox + col];
+            }
+            for (int q = sl; q < 2 * B; q += kSlotW) {
+                const int which = q / B, col = q - which * B;
+                const int y = which ? (A.oy + B) % L : (A.oy - 1 + L) % L;
+                hrow[which * 16 + col] = (uint8_t)lat[(int64_t)y * L + A.ox + col];
+            }
         }
     }
     uint32_t hl = 0, hr = 0;
@@ -131,14 +145,17 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     const uint32_t VM = (A.on && sl < B) ? ((1u << B) - 1u) : 0u;
     uint32_t S = 0, top = 0, bot = 0;
     if (A.on) {
-        for (int q = 0; q < B4; ++q) {
+        for (int q = 0; q < SB4; ++q) {
             if (sl < B)
-                S |= bytes_to_bits(*reinterpret_cast<const uint32_t *>(tile + sl * B + 4 * q))
+                S |= bytes_to_bits(*reinterpret_cast<const uint32_t *>(tile + sl * SB + 4 * q))
                      << (4 * q);
             top |= bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 4 * q)) << (4 * q);
             bot |= bytes_to_bits(*reinterpret_cast<const uint32_t *>(hrow + 16 + 4 * q))
                    << (4 * q);
         }
+        S &= VM;  // padding bytes decode to set bits: clear them
+        top &= (1u << B) - 1u;
+        bot &= (1u << B) - 1u;
     }
     auto planes = [&](uint32_t s) {
         uint32_t U = dpp<kRowShr + 1>(s);
@@ -329,16 +346,24 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
 
     // ---- write the tiles back through LDS
     if (A.on && sl < B) {
-        for (int q = 0; q < B4; ++q)
-            *reinterpret_cast<uint32_t *>(tile + sl * B + 4 * q) =
+        for (int q = 0; q < SB4; ++q)
+            *reinterpret_cast<uint32_t *>(tile + sl * SB + 4 * q) =
                 bits_to_bytes((S >> (4 * q)) & 0xFu);
     }
     wave_sync_lds();
     if (A.on) {
-        for (int q = sl; q < B * B4; q += kSlotW) {
-            const int row = q / B4, c4 = q - row * B4;
-            *reinterpret_cast<uint32_t *>(lat + (int64_t)(A.oy + row) * L + A.ox + 4 * c4) =
-                *reinterpret_cast<const uint32_t *>(tile + row * B + 4 * c4);
+        if ((B & 3) == 0) {
+            for (int q = sl; q < B * B4; q += kSlotW) {
+                const int row = q / B4, c4 = q - row * B4;
+                *reinterpret_cast<uint32_t *>(lat + (int64_t)(A.oy + row) * L + A.ox +
+                                              4 * c4) =
+                    *reinterpret_cast<const uint32_t *>(tile + row * SB + 4 * c4);
+            }
+        } else {
+            for (int q = sl; q < B * B; q += kSlotW) {
+                const int row = q / B, col = q - row * B;
+                lat[(int64_t)(A.oy + row) * L + A.ox + col] = (int8_t)tile[row * SB + col];
+            }
         }
     }
     wave_sync_lds();

@@ -60,9 +60,11 @@ def test_rate_table_rejects_bad_input(kmc):
 
 
 BAD = [
-    dict(L=16, tile=6, T=2.0),    # tile not a multiple of 4
+    dict(L=16, tile=6, T=2.0),    # L not a multiple of tile
     dict(L=24, tile=8, T=2.0),    # L/tile odd
-    dict(L=16, tile=16, T=2.0),   # one tile per dimension
+    dict(L=15, tile=5, T=2.0),    # L/tile odd
+    dict(L=2, tile=2, T=2.0),     # one domain with fewer than three rows
+    dict(L=8, tile=0, T=2.0),     # tile below 1
     dict(L=20, tile=8, T=2.0),    # L not a multiple of tile
     dict(L=256, tile=128, T=2.0), # tile above 64
     dict(L=16, tile=8, T=0.0),    # T must be positive

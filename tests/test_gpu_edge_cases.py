@@ -85,3 +85,46 @@ def test_calls_without_sweeps_or_record_points(torch_cuda, oracle_lib):
     assert list(rec[0]["sweep"]) == [7, 11]
     assert_records_equal(rec[0], orec, "sparse records")
     assert np.array_equal(lat.spins(0), o.spins())
+
+
+SHAPES = {
+    "tile1": dict(L=8, tile=1, T=2.2),                      # one site per domain
+    "tile2": dict(L=8, tile=2, T=2.4, h=0.1),
+    "tile3": dict(L=12, tile=3, T=2.0),
+    "tile5": dict(L=20, tile=5, T=2.6, rate_model=kmc.RATE_BARKER),
+    "tile6": dict(L=12, tile=6, T=2.4, rate_model=kmc.RATE_BARKER),   # the paper's 12^2, N_D = 4
+    "tile25": dict(L=100, tile=25, T=2.4, rate_model=kmc.RATE_BARKER, steps_per_visit=300),
+    "tile50": dict(L=100, tile=50, T=2.4, rate_model=kmc.RATE_BARKER, steps_per_visit=900),
+    "tile36_palin": dict(L=72, tile=36, T=2.3, schedule=kmc.SCHED_PALINDROME, steps_per_visit=500),
+    "single3": dict(L=3, tile=3, T=2.0),                    # N_D = 1: periodic in itself
+    "single12": dict(L=12, tile=12, T=2.4, rate_model=kmc.RATE_BARKER),
+    "single16_palin": dict(L=16, tile=16, T=2.1, h=0.2, schedule=kmc.SCHED_PALINDROME),
+    "single40": dict(L=40, tile=40, T=2.5, steps_per_visit=700),   # 64-bit rows
+}
+
+
+@pytest.mark.parametrize("form", ["phased", "flow", "persistent"])
+@pytest.mark.parametrize("case", list(SHAPES))
+def test_domain_shapes_match_oracle(torch_cuda, oracle_lib, case, form):
+    """Domain sides that are not multiples of 4 (byte-wise staging) and the
+    unpartitioned lattice as one periodic domain, in every execution form."""
+    d = SHAPES[case]
+    flags = {"phased": 0, "flow": kmc.F_FLOW, "persistent": kmc.F_PERSISTENT | kmc.F_MULTI}[form]
+    say(f"shape {case}, {form}")
+    lat = kmc.Lattice([d], 13)
+    lat.run(10, 5, flags)
+    o = oracle_for(oracle_lib, d, 13, 0)
+    orec = o.run(10, 5)
+    assert_replica_equal(lat, 0, o, lat.records()[0], orec, f"{case} {form}")
+    lat.close()
+
+
+def test_mixed_shapes_in_one_batch(torch_cuda, oracle_lib):
+    descs = list(SHAPES.values())
+    say("all shapes in one persistent batch")
+    lat = kmc.Lattice(descs, 29)
+    lat.run(6, 3, kmc.F_PERSISTENT)
+    rec = lat.records()
+    for rho, d in enumerate(descs):
+        o = oracle_for(oracle_lib, d, 29, rho)
+        assert_replica_equal(lat, rho, o, rec[rho], o.run(6, 3), f"batch {rho}")
