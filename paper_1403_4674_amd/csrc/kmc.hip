@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kmc.h"
@@ -69,6 +70,9 @@ struct kmc_ctx {
     int32_t nm_team[2] = {0, 0}, nm_solo[2] = {0, 0};
     int32_t *d_order_nm = nullptr;
     bool multi_auto = false;  // the multi-slot items keep >= 2 wavefronts per SIMD
+    // per row-mask width (B <= 32, B > 32): some replica is one periodic
+    // domain, so the launches of that width take the wrap-around kernels
+    bool wrap[2] = {false, false};
     int n_phase = 4;
 
     Rep *d_reps = nullptr;
@@ -293,6 +297,16 @@ void timed_launch(kmc_ctx *c, F fn) {
     c->tev.emplace_back(a, b);
 }
 
+// Calls f with std::true_type when replicas of row-mask width g include a
+// lattice that is one periodic domain, std::false_type otherwise.
+template <typename F>
+void with_wrap(const kmc_ctx *c, int g, F f) {
+    if (c->wrap[g])
+        f(std::true_type{});
+    else
+        f(std::false_type{});
+}
+
 template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K) {
     if (c->flow) {
@@ -301,15 +315,20 @@ void launch_sweep(kmc_ctx *c, KParams K) {
         timed_launch(c, [&] {
             if (c->n_tasks32) {
                 K.task_begin = 0;
-                hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE>),
-                                   dim3(c->n_phase * c->n_tasks32), dim3(64), 0, c->stream, K,
-                                   c->n_tasks32, c->d_done);
+                with_wrap(c, 0, [&](auto W) {
+                    hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value>),
+                                       dim3(c->n_phase * c->n_tasks32), dim3(64), 0, c->stream,
+                                       K, c->n_tasks32, c->d_done);
+                });
             }
             if (c->n_tasks > c->n_tasks32) {
                 const int nt = c->n_tasks - c->n_tasks32;
                 K.task_begin = c->n_tasks32;
-                hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE>), dim3(c->n_phase * nt),
-                                   dim3(64), 0, c->stream, K, nt, c->d_done);
+                with_wrap(c, 1, [&](auto W) {
+                    hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value>),
+                                       dim3(c->n_phase * nt), dim3(64), 0, c->stream, K, nt,
+                                       c->d_done);
+                });
             }
         });
         hipLaunchKernelGGL(kmcdev::k_sweep_end, dim3(c->n_rep), dim3(64), 0, c->stream, K);
@@ -322,14 +341,18 @@ void launch_sweep(kmc_ctx *c, KParams K) {
         timed_launch(c, [&] {
         if (c->n_tasks32) {
             K.task_begin = 0;
-            hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE>), dim3(c->n_tasks32),
-                               dim3(64), 0, c->stream, K, p);
+            with_wrap(c, 0, [&](auto W) {
+                hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE, decltype(W)::value>),
+                                   dim3(c->n_tasks32), dim3(64), 0, c->stream, K, p);
+            });
         }
         if (c->n_tasks > c->n_tasks32) {
             K.task_begin = c->n_tasks32;
-            hipLaunchKernelGGL((kmcdev::k_phase<uint64_t, SCORE>),
-                               dim3(c->n_tasks - c->n_tasks32), dim3(64), 0, c->stream, K,
-                               p);
+            with_wrap(c, 1, [&](auto W) {
+                hipLaunchKernelGGL((kmcdev::k_phase<uint64_t, SCORE, decltype(W)::value>),
+                                   dim3(c->n_tasks - c->n_tasks32), dim3(64), 0, c->stream, K,
+                                   p);
+            });
         }
         });
     }
@@ -360,12 +383,14 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t n_sweeps, uint32_t flags) 
         const int groups = std::max(1, std::min(nt[g] + (ns[g] + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         timed_launch(c, [&] {
-            if (g == 0)
-                hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE>), dim3(groups),
-                                   dim3(64 * waves), 0, c->stream, K, n_sweeps);
-            else
-                hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE>), dim3(groups),
-                                   dim3(64 * waves), 0, c->stream, K, n_sweeps);
+            with_wrap(c, g, [&](auto W) {
+                if (g == 0)
+                    hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE, decltype(W)::value>),
+                                       dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
+                else
+                    hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE, decltype(W)::value>),
+                                       dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
+            });
         });
     }
     if (multi) {
@@ -585,6 +610,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             for (int rho = 0; rho < n_rep; ++rho) {
                 Rep &rp = c->reps[rho];
                 if ((rp.B > 32) != (pass == 1)) continue;
+                if (rp.NT == 1) c->wrap[pass] = true;
                 rp.task_off = (int32_t)task_rep.size();
                 for (int i = 0; i < std::max(rp.ND / 4, 1); ++i) task_rep.push_back(rho);
                 if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();

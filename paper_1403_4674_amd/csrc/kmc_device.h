@@ -440,6 +440,49 @@ __device__ __forceinline__ MT class_mask(int c, MT S, const Planes<MT> &P, MT VM
     return (S ^ xS) & (P.s0 ^ x0) & (P.s1 ^ x1) & (P.s2 ^ x2) & VM;
 }
 
+// The same selection for a class c held in a scalar register, as in the
+// event chain: the four complement masks are sign-extended table bits taken
+// by the scalar unit (s_bfe_i32 with width 1 gives 0 or all ones), and the
+// mask is a chain of t & (plane ^ x) steps, one 3-input bit operation each
+// (truth table 0x60 = src0 & (src1 ^ src2)).
+struct ClassSel {
+    uint32_t xS, x0, x1, x2;
+};
+
+__device__ __forceinline__ uint32_t sgpr_sign_bit(uint32_t table, uint32_t c) {
+    uint32_t r;
+    asm("s_bfe_i32 %0, %1, %2" : "=s"(r) : "s"(table), "s"(c | 0x10000u) : "scc");
+    return r;
+}
+
+__device__ __forceinline__ ClassSel class_sel(int c) {
+    return ClassSel{sgpr_sign_bit(kInvS, (uint32_t)c), sgpr_sign_bit(kInvK0, (uint32_t)c),
+                    sgpr_sign_bit(kInvK1, (uint32_t)c), sgpr_sign_bit(kInvK2, (uint32_t)c)};
+}
+
+__device__ __forceinline__ uint32_t and_xor(uint32_t t, uint32_t v, uint32_t x) {
+    return __builtin_amdgcn_bitop3_b32(t, v, x, 0x60);
+}
+
+template <typename MT>
+__device__ __forceinline__ MT class_mask(const ClassSel &q, MT S, const Planes<MT> &P, MT VM) {
+    if constexpr (sizeof(MT) == 8) {
+        auto half = [&](int h) {
+            const uint32_t sh = 32 * h;
+            uint32_t t = and_xor((uint32_t)(VM >> sh), (uint32_t)(S >> sh), q.xS);
+            t = and_xor(t, (uint32_t)(P.s0 >> sh), q.x0);
+            t = and_xor(t, (uint32_t)(P.s1 >> sh), q.x1);
+            return and_xor(t, (uint32_t)(P.s2 >> sh), q.x2);
+        };
+        return (MT)half(0) | ((MT)half(1) << 32);
+    } else {
+        uint32_t t = and_xor(VM, S, q.xS);
+        t = and_xor(t, P.s0, q.x0);
+        t = and_xor(t, P.s1, q.x1);
+        return and_xor(t, P.s2, q.x2);
+    }
+}
+
 template <typename MT>
 __device__ __forceinline__ int class_at(MT S, const Planes<MT> &P, int b) {
     return 5 * (int)((S >> b) & 1) + (int)((P.s0 >> b) & 1) +
@@ -492,8 +535,11 @@ struct VisitOut {
 // `lat` (side L, domain side B).  Executed by one full wavefront; `lds`
 // points at this wavefront's kLdsPerWave bytes.  The domain's compensated
 // clock in *dom is advanced; the changes of M, B and the event count are
-// returned (and the score when SCORE).
-template <typename MT, bool SCORE>
+// returned (and the score when SCORE).  WRAP admits replicas whose lattice
+// is a single periodic domain; without it the wrap-around bookkeeping is
+// compiled out of the event chain (every instruction of the chain costs an
+// issue slot when a wavefront runs alone on its SIMD).
+template <typename MT, bool SCORE, bool WRAP>
 __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                                  const Rates *__restrict__ rt, int oy, int ox,
                                  uint32_t d, uint32_t vis, uint32_t w,
@@ -593,7 +639,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
     // a lattice that is one domain is periodic in itself: its boundary
     // neighbours are its own sites and change during the visit
-    const int wrapB = rp.NT == 1 ? B : 0;
+    const int wrapB = WRAP && rp.NT == 1 ? B : 0;
 
     // Score.  A run of m null ticks adds m d ln(1 - R_w/n_d)/d theta =
     // -m sum_c n_c a_c / (n_d - R_w) (a_c = w_c d ln w_c/d theta), linear in
@@ -628,14 +674,12 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         uint64_t left = __ballot(valid);  // ticks of the batch not yet decided
         double Rb = 0.0;                  // this lane's R before its event (0: none)
         int pos = 0;
-        for (;;) {
-            const uint64_t cand = __ballot(x < R) & left;
-            if (!cand) {
-                m_null += (uint32_t)__popcll(left);
-                break;
-            }
+        // the first undecided tick below R is the next event; the ticks
+        // before it are nulls
+        uint64_t cand = __ballot(x < R) & left;
+        while (cand) {
             const int e = __builtin_ctzll(cand);
-            left &= ~(cand ^ (cand - 1));  // drop the ticks up to and including e
+            left &= ~1ull << e;  // drop the ticks up to and including e
             m_null += (uint32_t)(e - pos);
             const double xe = rdl_f64(x, e);
             if (lane == e) Rb = R;
@@ -645,11 +689,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             // at once as trunc((xe - P_{c-1} + 1/2) fl(1/r_c)): the quotient
             // lies at least 1/(2 r_c) >= 2^-33 from an integer and the product
             // is within 2^-39 of it (quotient < 2^13), so the truncation is
-            // exact; other lanes are clamped into range and discarded.
+            // exact.  Only lane c's quotient is read, then converted.
             const int c = __builtin_ctzll(__ballot(xe < Pinc));
             const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
-            const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
-            const uint32_t j = rdl32(jl, c);
+            const uint32_t j = (uint32_t)rdl_f64(q, c);
 
             if constexpr (SCORE) {
                 if (m_null) null_run(m_null);
@@ -659,7 +702,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             // member j of class c in ascending row-major order: the row by a
             // scan of per-row counts, the column by counting the row's
             // members below each lane (mbcnt)
-            const MT cm = class_mask<MT>(c, S, P, VM);
+            const MT cm = class_mask<MT>(class_sel(c), S, P, VM);
             const uint32_t cnt = (uint32_t)popc(cm);
             const uint32_t incl = sizeof(MT) == 4 ? scan32(cnt) : scan64(cnt);
             const int ys = __builtin_ctzll(__ballot(incl > j));
@@ -717,7 +760,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             if (on_row) S ^= bx;
             planes_step<MT>(P, on_row ? mrow : (adj ? bx : (MT)0), !up);
             pos = e + 1;
+            cand = __ballot(x < R) & left;
         }
+        m_null += (uint32_t)__popcll(left);  // the batch's trailing nulls
         // residence times -ln(u)/R of this batch's events, kept per lane
         if (Rb != 0.0) {
             const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
@@ -820,7 +865,7 @@ __device__ inline double replica_time(const KParams &K, const Rep &rp, int lane)
 
 // Phase p of the current sweep: one wavefront per (replica, domain of the
 // phase's colour).  Launched once per phase; domains of a colour commute.
-template <typename MT, bool SCORE>
+template <typename MT, bool SCORE, bool WRAP>
 __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
     const int task = K.task_begin + (int)blockIdx.x;
@@ -832,7 +877,7 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     if (col < 0 || task - rp.task_off >= domains_of_colour(rp, col)) return;
     int d, oy, ox;
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
-    const VisitOut o = visit_domain<MT, SCORE>(
+    const VisitOut o = visit_domain<MT, SCORE, WRAP>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
         (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
     if (__lane_id() == 0) {
@@ -875,7 +920,7 @@ constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;
 // phase.  Blocks are numbered phase-major, so a block only waits on blocks
 // numbered before it.  A wait that exceeds kFlowMaxPolls polls sets ctl->err
 // and gives up (the host reports the run as failed), so no wave can hang.
-template <typename MT, bool SCORE>
+template <typename MT, bool SCORE, bool WRAP>
 __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *done) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
     const int p = (int)blockIdx.x / n_tasks;
@@ -920,7 +965,7 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
         wait_for(ty, tx);  // the palindrome's second visit waits for the first
     }
     __builtin_amdgcn_wave_barrier();
-    const VisitOut o = visit_domain<MT, SCORE>(
+    const VisitOut o = visit_domain<MT, SCORE, WRAP>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
         (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
     if (__lane_id() == 0) {
@@ -1030,7 +1075,7 @@ struct TeamShared {
 // the workgroup).  In each colour phase wavefront `wave` takes the phase's
 // domains wave, wave + nw, ...; with a team a workgroup barrier separates the
 // phases (domains of one colour never touch, so the split changes no result).
-template <typename MT, bool SCORE>
+template <typename MT, bool SCORE, bool WRAP>
 __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lane,
                             uint8_t *lds, TeamShared *ts, int64_t sweep0,
                             int64_t run_done0, int64_t n_sweeps, int64_t rec_every,
@@ -1049,7 +1094,7 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
             for (int i2 = wave; i2 < per_colour; i2 += nw) {
                 int d, oy, ox;
                 colour_domain(rp, col, i2, &d, &oy, &ox);
-                const VisitOut o = visit_domain<MT, SCORE>(
+                const VisitOut o = visit_domain<MT, SCORE, WRAP>(
                     K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
                     (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
                 dM += o.dM;
@@ -1102,7 +1147,7 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
 // a whole workgroup (costliest first), then n_solo replicas run by single
 // wavefronts (costliest first).  Every wavefront leaves once both queues
 // are drained.  One call site keeps the domain process inlined once.
-template <typename MT, bool SCORE>
+template <typename MT, bool SCORE, bool WRAP>
 __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
     KParams K, int64_t n_sweeps) {
     __shared__ __attribute__((aligned(16)))
@@ -1148,7 +1193,7 @@ __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
         rho = __builtin_amdgcn_readfirstlane(rho);
         me = __builtin_amdgcn_readfirstlane(me);
         nw = __builtin_amdgcn_readfirstlane(nw);
-        run_replica<MT, SCORE>(K, rho, me, nw, lane, lds, &ts, sweep0, run_done0, n_sweeps,
+        run_replica<MT, SCORE, WRAP>(K, rho, me, nw, lane, lds, &ts, sweep0, run_done0, n_sweeps,
                                rec_every, rec_base);
     }
 }

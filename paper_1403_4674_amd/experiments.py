@@ -7,7 +7,8 @@ persistent launch.  The analysis (tau, eta, chi^2) is `analysis.py`.
 
     python -m paper_1403_4674_amd.experiments --L 12 --traj 500
 
-prints one JSON line per setting and a summary line.
+prints one JSON line per setting and a summary line; `--save FILE.npz`
+also keeps every setting's trajectories (steps, M, B) for re-analysis.
 """
 import json
 import time
@@ -80,6 +81,41 @@ def analyse(results, L, eq_fraction=0.5, max_lag_samples=400):
     return out
 
 
+def save_study(path, results, L):
+    """Trajectories of every setting as compact arrays: M and B fit in 32
+    bits for L <= 2^14; steps are shared by all trajectories of a setting."""
+    arrays = {}
+    for k, r in enumerate(results):
+        rec = r["rec"]
+        arrays[f"s{k}_steps"] = rec["steps"][0].astype(np.int64)
+        arrays[f"s{k}_M"] = rec["M"].astype(np.int32)
+        arrays[f"s{k}_B"] = rec["B"].astype(np.int32)
+    arrays["labels"] = np.array([r["label"] for r in results])
+    arrays["tile"] = np.array([r["tile"] for r in results])
+    arrays["NI"] = np.array([r["NI"] for r in results])
+    arrays["L"] = np.array(L)
+    np.savez_compressed(path, **arrays)
+
+
+def load_study(path):
+    """Inverse of save_study: a list of dicts with `label`, `tile`, `NI`, `ND`
+    and `rec` (structured records with the fields steps, M, B), as
+    `analyse` takes them (timings are not kept)."""
+    z = np.load(path)
+    L = int(z["L"])
+    out = []
+    for k, label in enumerate(z["labels"]):
+        M = z[f"s{k}_M"]
+        rec = np.zeros(M.shape, [("steps", "<i8"), ("M", "<i8"), ("B", "<i8")])
+        rec["steps"] = z[f"s{k}_steps"][None, :]
+        rec["M"] = M
+        rec["B"] = z[f"s{k}_B"]
+        B = int(z["tile"][k])
+        out.append(dict(label=str(label), tile=B, NI=int(z["NI"][k]), ND=(L // B) ** 2, rec=rec,
+                        sec=float("nan"), ticks=0))
+    return out, L
+
+
 def main():
     import argparse
 
@@ -91,11 +127,14 @@ def main():
     ap.add_argument("--traj", type=int, default=500)
     ap.add_argument("--steps", type=int, default=160000)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--save", default="", help="write the trajectories to this .npz")
     args = ap.parse_args()
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
     res = run_study(kmc, args.L, args.traj, args.steps, seed=args.seed)
     rows = analyse(res, args.L)
+    if args.save:
+        save_study(args.save, res, args.L)
     for row in rows:
         print(json.dumps(row), flush=True)
     print(json.dumps({"L": args.L, "trajectories": args.traj, "steps": args.steps,

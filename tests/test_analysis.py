@@ -93,3 +93,23 @@ def test_observables_from_records():
     r = analysis.start_record(analysis.circle_initial_condition(12), 3,
                               [("M", "<i8"), ("B", "<i8")])
     assert r.shape == (3, 1) and int(r["M"][0, 0]) == 8
+
+
+def test_study_save_and_load_round_trip(tmp_path):
+    from paper_1403_4674_amd import experiments
+    rng = np.random.default_rng(3)
+    res = []
+    for label, B, NI in [("reference", 12, 144), ("checkerboard N_D=4 N_I=2", 6, 2)]:
+        rec = np.zeros((5, 7), [("steps", "<i8"), ("M", "<i8"), ("B", "<i8"), ("t", "<f8")])
+        rec["steps"] = np.arange(7)[None, :] * 144
+        rec["M"] = rng.integers(-144, 145, (5, 7))
+        rec["B"] = rng.integers(-288, 289, (5, 7))
+        res.append(dict(label=label, tile=B, NI=NI, ND=(12 // B) ** 2, rec=rec, sec=1.0, ticks=1))
+    p = tmp_path / "study.npz"
+    experiments.save_study(str(p), res, 12)
+    back, L = experiments.load_study(str(p))
+    assert L == 12 and [r["label"] for r in back] == [r["label"] for r in res]
+    for a, b in zip(res, back):
+        assert (a["tile"], a["NI"], a["ND"]) == (b["tile"], b["NI"], b["ND"])
+        for f in ("steps", "M", "B"):
+            assert np.array_equal(a["rec"][f], b["rec"][f])
