@@ -483,6 +483,19 @@ __device__ __forceinline__ MT class_mask(const ClassSel &q, MT S, const Planes<M
     }
 }
 
+// Per-lane form (the class differs between the slots of a wavefront): the
+// vector signed bit-field extract gives 0 or all ones per lane.
+__device__ __forceinline__ uint32_t vgpr_sign_bit(uint32_t table, uint32_t c) {
+    uint32_t r;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "s"(table), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ ClassSel class_sel_lane(uint32_t c) {
+    return ClassSel{vgpr_sign_bit(kInvS, c), vgpr_sign_bit(kInvK0, c), vgpr_sign_bit(kInvK1, c),
+                    vgpr_sign_bit(kInvK2, c)};
+}
+
 template <typename MT>
 __device__ __forceinline__ int class_at(MT S, const Planes<MT> &P, int b) {
     return 5 * (int)((S >> b) & 1) + (int)((P.s0 >> b) & 1) +

@@ -261,7 +261,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             if (act) m_null = 0;
 
             // member j: row by a row scan of per-row counts, column by rank
-            const uint32_t cm = class_mask<uint32_t>(c, S, P, VM);
+            const uint32_t cm = class_mask<uint32_t>(class_sel_lane((uint32_t)c), S, P, VM);
             const uint32_t cnt = (uint32_t)__popc(cm);
             const uint32_t incl = scan_row(cnt);
             const uint32_t yseg = seg16(__ballot(incl > j), slot);
