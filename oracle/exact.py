@@ -100,36 +100,53 @@ class TickKernel:
         return v
 
 
-def checkerboard(L, B):
-    """Domains of side B in row-major order and their colours
-    2*(ty mod 2) + (tx mod 2)."""
-    NT = L // B
+def partition(L, Bx, By=None):
+    """Domains Bx wide and By high in row-major order over the domain grid,
+    their colours and the number of colours.  Each axis of n domains is
+    coloured with one colour (n = 1), t mod 2 (n even), or t mod 2 with the
+    last domain given a third colour (n odd); the colour is ax + cx ay."""
+    By = By or Bx
+    NTx, NTy = L // Bx, L // By
+
+    def axis(t, n):
+        return 0 if n == 1 else (2 if n % 2 and t == n - 1 else t % 2)
+
+    def ncol(n):
+        return 1 if n == 1 else (3 if n % 2 else 2)
+
     doms, cols = [], []
-    for ty in range(NT):
-        for tx in range(NT):
-            sites = [(ty * B + ly) * L + tx * B + lx
-                     for ly in range(B) for lx in range(B)]
-            doms.append(sites)
-            cols.append(2 * (ty % 2) + (tx % 2))
+    for ty in range(NTy):
+        for tx in range(NTx):
+            doms.append([(ty * By + ly) * L + tx * Bx + lx
+                         for ly in range(By) for lx in range(Bx)])
+            cols.append(axis(tx, NTx) + ncol(NTx) * axis(ty, NTy))
+    return doms, cols, ncol(NTx) * ncol(NTy)
+
+
+def checkerboard(L, B):
+    """Square domains of side B (4 colours when L/B is even)."""
+    doms, cols, _ = partition(L, B, B)
     return doms, cols
 
 
 class SweepOperator:
     """T_SEQ(Lambda) for one colour order and T_PAR, the uniform mixture over
-    all 4! colour orders (Eq. (replica detailed balance of sequential tm) and
-    Eq. (sum of sequential tms)), or the fixed palindrome ABCDDCBA."""
+    all n! orders of the n colours (Eq. (replica detailed balance of
+    sequential tm) and Eq. (sum of sequential tms)), or the fixed palindrome
+    0 1 .. n-1 n-1 .. 1 0.  Domains are B wide and By (default B) high."""
 
     def __init__(self, L, B, J, h, T, model=0, NI=None, quantise=False,
-                 palindrome=False):
-        self.doms, self.cols = checkerboard(L, B)
+                 palindrome=False, By=None):
+        self.doms, self.cols, self.ncol = partition(L, B, By)
         self.kern = [TickKernel(L, d, J, h, T, model, quantise) for d in self.doms]
-        self.NI = NI if NI else B * B
+        self.NI = NI if NI else B * (By or B)
         self.palindrome = palindrome
 
     def orders(self):
+        n = self.ncol
         if self.palindrome:
-            return [(0, 1, 2, 3, 3, 2, 1, 0)]
-        return list(itertools.permutations(range(4)))
+            return [tuple(range(n)) + tuple(reversed(range(n)))]
+        return list(itertools.permutations(range(n)))
 
     def seq(self, p, order):
         for c in order:

@@ -19,13 +19,16 @@
  *  R2  Rates: Barker 1/(1+e^{dE/T}) as printed, or Metropolis
  *      min(1, e^{-dE/T}).  dE = 2 s (J n + h), n = sum of the 4 neighbours;
  *      the field h extends Eq. (Hamiltonian Definition).
- *  R3  Domains of one colour of a 4-colour checkerboard never touch, so the
- *      paper's remark that the order of non-interacting domains is
- *      irrelevant (Sec. 2.2) lets the schedule be a permutation of the four
- *      colours, drawn uniformly each sweep (w(L) = 1/4!, closed under
- *      reversal, Eq. (sum of sequential tms)), or the self-reverse
- *      palindrome A B C D D C B A.  Domains of a colour run in ascending
- *      index order; they commute.
+ *  R3  Domains are Bx wide and By high (checkerboards, vertical stripes with
+ *      By = L, a single domain).  The domain grid is coloured per axis: one
+ *      colour for a single domain, t mod 2 for an even count, t mod 2 with
+ *      the last domain given colour 2 for an odd count; the colour is
+ *      ax + cx ay.  Domains of one colour never touch, so the paper's remark
+ *      that the order of non-interacting domains is irrelevant (Sec. 2.2)
+ *      lets the schedule be a permutation of the n colours, drawn uniformly
+ *      each sweep (w(L) = 1/n!, closed under reversal, Eq. (sum of
+ *      sequential tms)), or the self-reverse palindrome 0 1 .. n-1 n-1 .. 1 0.
+ *      Domains of a colour run in ascending index order; they commute.
  *  R4  Clock: the residence time of Eq. (Poisson Distribution) is drawn per
  *      accepted event as -ln(u)/R_w with R_w = R / 2^32 the domain's total
  *      rate before the event (the paper advances by the mean; it states both
@@ -130,35 +133,56 @@ int kmco_rates(double J, double h, double T, int32_t model,
 
 /* -------------------------------------------------------------- schedule */
 
-void kmco_perm_from_index(int32_t idx, int32_t perm[4])
+static int32_t factorial(int32_t n)
 {
-    /* lexicographic rank -> permutation of {0,1,2,3} */
-    int avail[4] = {0, 1, 2, 3};
-    int navail = 4;
-    int radix[3] = {6, 2, 1};
-    for (int i = 0; i < 3; ++i) {
-        int a = idx / radix[i];
-        idx %= radix[i];
+    int32_t f = 1;
+    for (int32_t i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+void kmco_perm_from_index_n(int32_t idx, int32_t n, int32_t *perm)
+{
+    /* lexicographic rank -> permutation of {0..n-1}: digit i of the rank in
+     * the factorial number system picks among the values still unused */
+    int avail[9];
+    int navail = n;
+    for (int i = 0; i < n; ++i) avail[i] = i;
+    for (int i = 0; i < n; ++i) {
+        int32_t radix = factorial(n - 1 - i);
+        int a = idx / radix;
+        idx %= radix;
         perm[i] = avail[a];
         for (int j = a; j < navail - 1; ++j) avail[j] = avail[j + 1];
         --navail;
     }
-    perm[3] = avail[0];
 }
 
-int32_t kmco_schedule_index(uint64_t seed, int32_t replica, int64_t sweep)
+void kmco_perm_from_index(int32_t idx, int32_t perm[4])
 {
-    /* Uniform on [0,24): Lemire multiply-high with rejection of the
-     * (2^32 mod 24) = 16 smallest low halves, words taken in order. */
+    kmco_perm_from_index_n(idx, 4, perm);
+}
+
+int32_t kmco_schedule_index_n(uint64_t seed, int32_t replica, int64_t sweep,
+                              int32_t n_perm)
+{
+    /* Uniform on [0,n): Lemire multiply-high with rejection of the
+     * (2^32 mod n) smallest low halves, words taken in order. */
+    const uint32_t n = (uint32_t)n_perm;
+    const uint32_t thr = (uint32_t)(0u - n) % n;
     for (uint32_t call = 0;; ++call) {
         uint32_t o[4];
         draw(seed, call, STREAM_SCHED << 24, (uint32_t)sweep,
              (uint32_t)replica, o);
         for (int i = 0; i < 4; ++i) {
-            uint64_t m = (uint64_t)o[i] * 24u;
-            if ((uint32_t)m >= 16u) return (int32_t)(m >> 32);
+            uint64_t m = (uint64_t)o[i] * n;
+            if ((uint32_t)m >= thr) return (int32_t)(m >> 32);
         }
     }
+}
+
+int32_t kmco_schedule_index(uint64_t seed, int32_t replica, int64_t sweep)
+{
+    return kmco_schedule_index_n(seed, replica, sweep, 24);
 }
 
 uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
@@ -189,7 +213,9 @@ uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
 /* ---------------------------------------------------------------- state */
 
 struct kmco_state {
-    int L, B, NT, ND, nd, NI, sched, model;
+    int L, Bx, By, NTx, NTy, ND, nd, NI, sched, model;
+    int ncol;              /* colours of the domain grid                  */
+    int32_t *colour;       /* [ND]                                        */
     double J, h, T;
     uint64_t seed;
     int replica;
@@ -222,19 +248,25 @@ static int site_class(const kmco_state *s, int y, int x)
     return 5 * up + k;
 }
 
+/* Colour of position t on an axis of n domains, and the axis's colours. */
+static int axis_colour(int t, int n) { return n == 1 ? 0 : (n % 2 && t == n - 1) ? 2 : t % 2; }
+static int axis_colours(int n) { return n == 1 ? 1 : n % 2 ? 3 : 2; }
+
 kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
                         const int8_t *given)
 {
     if (!d || d->L < 1 || d->tile < 1 || d->L % d->tile) return NULL;
-    int NT = d->L / d->tile;
-    if (NT > 1 && NT % 2) return NULL; /* 4-colour checkerboard needs even NT */
+    const int By = d->tile_rows ? d->tile_rows : d->tile;
+    if (By < 1 || d->L % By) return NULL;
     if (d->steps_per_visit < 0) return NULL;
     if (d->schedule != KMCO_SCHED_RANDOM_PERM &&
         d->schedule != KMCO_SCHED_PALINDROME) return NULL;
     kmco_state *s = (kmco_state *)calloc(1, sizeof(*s));
     if (!s) return NULL;
-    s->L = d->L; s->B = d->tile; s->NT = NT; s->ND = NT * NT;
-    s->nd = d->tile * d->tile;
+    s->L = d->L; s->Bx = d->tile; s->By = By;
+    s->NTx = d->L / d->tile; s->NTy = d->L / By;
+    s->ND = s->NTx * s->NTy;
+    s->nd = s->Bx * s->By;
     s->NI = d->steps_per_visit ? d->steps_per_visit : s->nd;
     s->sched = d->schedule; s->model = d->rate_model;
     s->J = d->J; s->h = d->h; s->T = d->T;
@@ -251,11 +283,16 @@ kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
     s->nw = (s->nd + 63) / 64;
     s->bits = (uint64_t *)calloc((size_t)10 * s->nw, sizeof(uint64_t));
     s->cls = (int8_t *)malloc(s->nd);
+    s->colour = (int32_t *)malloc(sizeof(int32_t) * s->ND);
     if (!s->spin || !s->clk_sum || !s->clk_comp || !s->dom_events ||
-        !s->bits || !s->cls) {
+        !s->bits || !s->cls || !s->colour) {
         kmco_destroy(s);
         return NULL;
     }
+    const int cx = axis_colours(s->NTx);
+    s->ncol = cx * axis_colours(s->NTy);
+    for (int q = 0; q < s->ND; ++q)
+        s->colour[q] = axis_colour(q % s->NTx, s->NTx) + cx * axis_colour(q / s->NTx, s->NTy);
     for (size_t i = 0; i < N; ++i) {
         if (d->init == KMCO_INIT_ALL_UP) {
             s->spin[i] = 1;
@@ -281,7 +318,7 @@ void kmco_destroy(kmco_state *s)
 {
     if (!s) return;
     free(s->spin); free(s->clk_sum); free(s->clk_comp); free(s->dom_events);
-    free(s->bits); free(s->cls);
+    free(s->bits); free(s->cls); free(s->colour);
     free(s);
 }
 
@@ -355,7 +392,7 @@ static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
 {
     int64_t cnt[10] = {0};
     for (int k = 0; k < s->nd; ++k) {
-        int c = site_class(s, oy + k / s->B, ox + k % s->B);
+        int c = site_class(s, oy + k / s->Bx, ox + k % s->Bx);
         cnt[c]++;
         if (c != s->cls[k]) s->check_fail++;
         if (!((s->bits[(size_t)c * s->nw + (k >> 6)] >> (k & 63)) & 1u))
@@ -371,12 +408,12 @@ static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
 static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
                          int flags, double *score)
 {
-    const int B = s->B, L = s->L;
-    const int oy = (d / s->NT) * B, ox = (d % s->NT) * B;
+    const int Bx = s->Bx, By = s->By, L = s->L;
+    const int oy = (d / s->NTx) * By, ox = (d % s->NTx) * Bx;
     int64_t n[10] = {0};
     memset(s->bits, 0, sizeof(uint64_t) * 10 * (size_t)s->nw);
     for (int k = 0; k < s->nd; ++k)
-        set_class(s, k, site_class(s, oy + k / B, ox + k % B), n);
+        set_class(s, k, site_class(s, oy + k / Bx, ox + k % Bx), n);
 
     uint64_t m_null = 0; /* null ticks since the last event (score) */
     for (int t = 0; t < s->NI; ++t) {
@@ -403,7 +440,7 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         }
         uint64_t j = (x - P) / s->r[c];
         int k = select_member(s, c, j);
-        int ly = k / B, lx = k % B;
+        int ly = k / Bx, lx = k % Bx;
         int gy = oy + ly, gx = ox + lx;
 
         if (flags & KMCO_F_SCORE) {
@@ -430,8 +467,8 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         for (int a = 0; a < 5; ++a) {
             int yy = wrap(gy + dy[a], L), xx = wrap(gx + dx[a], L);
             int ry = wrap(yy - oy, L), rx = wrap(xx - ox, L);
-            if (ry >= B || rx >= B) continue; /* halo site: frozen */
-            int kk = ry * B + rx, dup = 0;
+            if (ry >= By || rx >= Bx) continue; /* halo site: frozen */
+            int kk = ry * Bx + rx, dup = 0;
             for (int b = 0; b < na; ++b) dup |= aff[b] == kk;
             if (!dup) aff[na++] = kk;
         }
@@ -439,7 +476,7 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         s->spin[gy * L + gx] = (int8_t)-s->spin[gy * L + gx];
         for (int a = 0; a < na; ++a)
             set_class(s, aff[a],
-                      site_class(s, oy + aff[a] / B, ox + aff[a] % B), n);
+                      site_class(s, oy + aff[a] / Bx, ox + aff[a] % Bx), n);
         s->events++;
         s->dom_events[d]++;
         if (flags & KMCO_F_CHECK) check_classes(s, oy, ox, n);
@@ -478,24 +515,27 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
 {
     if (!s || n_sweeps < 0 || record_every < 1) return -1;
     if ((flags & KMCO_F_SCORE) && !score) return -1;
-    static const int pal[8] = {0, 1, 2, 3, 3, 2, 1, 0};
+    const int nc = s->ncol;
     int64_t nrec = 0;
     double dummy[2];
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const int64_t w = s->sweep;
-        int order[8], visit[8], nphase;
+        int order[18], visit[18], nphase;
         if (s->sched == KMCO_SCHED_PALINDROME) {
-            nphase = 8;
-            for (int p = 0; p < 8; ++p) {
-                order[p] = pal[p];
-                visit[p] = p < 4 ? 0 : 1;
+            /* 0 1 .. n-1, then the same colours backwards (second visits) */
+            nphase = 2 * nc;
+            for (int p = 0; p < nc; ++p) {
+                order[p] = p;
+                visit[p] = 0;
+                order[nphase - 1 - p] = p;
+                visit[nphase - 1 - p] = 1;
             }
         } else {
-            int32_t perm[4];
-            kmco_perm_from_index(kmco_schedule_index(s->seed, s->replica, w),
-                                 perm);
-            nphase = 4;
-            for (int p = 0; p < 4; ++p) {
+            int32_t perm[9];
+            kmco_perm_from_index_n(
+                kmco_schedule_index_n(s->seed, s->replica, w, factorial(nc)), nc, perm);
+            nphase = nc;
+            for (int p = 0; p < nc; ++p) {
                 order[p] = perm[p];
                 visit[p] = 0;
             }
@@ -504,12 +544,9 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
                          ? (nrec < rec_cap ? score + 2 * nrec : dummy)
                          : NULL;
         for (int p = 0; p < nphase; ++p) {
-            for (int d = 0; d < s->ND; ++d) {
-                int ty = d / s->NT, tx = d % s->NT;
-                int colour = 2 * (ty & 1) + (tx & 1);
-                if (colour == order[p])
+            for (int d = 0; d < s->ND; ++d)
+                if (s->colour[d] == order[p])
                     visit_domain(s, d, visit[p], w, flags, sc);
-            }
         }
         s->sweep++;
         if ((i + 1) % record_every == 0) {
@@ -543,3 +580,11 @@ int kmco_get_domain_events(const kmco_state *s, int64_t *events)
 }
 
 int64_t kmco_check_failures(const kmco_state *s) { return s ? s->check_fail : -1; }
+
+int kmco_get_partition(const kmco_state *s, int32_t *colour, int32_t *n_colours)
+{
+    if (!s) return -1;
+    if (colour) memcpy(colour, s->colour, sizeof(int32_t) * s->ND);
+    if (n_colours) *n_colours = s->ncol;
+    return 0;
+}

@@ -14,11 +14,11 @@
  *   - single-site kernel with self-loops, Appendix A, Eq. (Glauber_TM):
  *     selection probability 1/n_d inside a domain, acceptance w (Barker form
  *     as printed, or Metropolis min(1, exp(-dE/T)));
- *   - equal, fixed domains with a frozen halo, each run for N_I steps,
- *     Sec. 2.2 and Fig. 1;
+ *   - equal, fixed rectangular domains with a frozen halo, each run for N_I
+ *     steps, Sec. 2.2 and Fig. 1 (checkerboards, stripes, one domain);
  *   - a schedule drawn uniformly each sweep, Eq. (schedule) and
  *     Eq. (sum of sequential tms); non-interacting domains (one colour of a
- *     4-colour checkerboard) run in one phase, Sec. 2.2;
+ *     proper colouring of the domain grid) run in one phase, Sec. 2.2;
  *   - n-fold-way residence time tau = 1/R per event, Eq. (Poisson
  *     Distribution) and the text after it;
  *   - integer step count s += N_I * N_D per sweep, Eq. (CK_parallel in s);
@@ -42,11 +42,12 @@ enum { KMCO_F_SCORE = 1, KMCO_F_CHECK = 2 };
 typedef struct {
     double J, h, T;
     int32_t L;               /* periodic L x L lattice                    */
-    int32_t tile;            /* B: square domain side, L % B == 0          */
+    int32_t tile;            /* Bx: domain width, L % Bx == 0              */
     int32_t steps_per_visit; /* N_I ticks per domain visit; 0 means B*B    */
     int32_t rate_model;      /* KMCO_METROPOLIS or KMCO_BARKER             */
     int32_t schedule;        /* KMCO_SCHED_*                                */
     int32_t init;            /* KMCO_INIT_*                                 */
+    int32_t tile_rows;       /* By: domain height, L % By == 0; 0 means Bx  */
 } kmco_desc;
 
 typedef struct {
@@ -67,9 +68,20 @@ void kmco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int kmco_rates(double J, double h, double T, int32_t model,
                uint64_t r[10], double w[10], double gJ[10], double gh[10]);
 
-/* Index in [0,24) of the colour permutation for (seed, replica, sweep). */
+/* Index in [0, n_perm) of the colour permutation for (seed, replica, sweep);
+ * n_perm = n_colours!.  kmco_schedule_index is the 4-colour case (24). */
+int32_t kmco_schedule_index_n(uint64_t seed, int32_t replica, int64_t sweep,
+                              int32_t n_perm);
 int32_t kmco_schedule_index(uint64_t seed, int32_t replica, int64_t sweep);
+/* Lexicographic permutation of {0..n-1} of rank idx (n <= 9). */
+void kmco_perm_from_index_n(int32_t idx, int32_t n, int32_t *perm);
 void kmco_perm_from_index(int32_t idx, int32_t perm[4]);
+
+/* Colour of each domain (row-major over the domain grid) and the number of
+ * colours: per axis 1 colour for a single domain, 2 for an even count
+ * (t mod 2), 3 for an odd count (t mod 2, the last domain 2); the domain's
+ * colour is ax + cx * ay. */
+int kmco_get_partition(const kmco_state *s, int32_t *colour, int32_t *n_colours);
 
 /* Uniform slot in [0, n) for one tick, with rejection and retries. */
 uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,

@@ -19,7 +19,8 @@ class Desc(C.Structure):
     _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
                 ("L", C.c_int32), ("tile", C.c_int32),
                 ("steps_per_visit", C.c_int32), ("rate_model", C.c_int32),
-                ("schedule", C.c_int32), ("init", C.c_int32)]
+                ("schedule", C.c_int32), ("init", C.c_int32),
+                ("tile_rows", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -47,6 +48,10 @@ def lib():
         L.kmco_schedule_index.argtypes = [C.c_uint64, C.c_int32, C.c_int64]
         L.kmco_schedule_index.restype = C.c_int32
         L.kmco_perm_from_index.argtypes = [C.c_int32, P]
+        L.kmco_schedule_index_n.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32]
+        L.kmco_schedule_index_n.restype = C.c_int32
+        L.kmco_perm_from_index_n.argtypes = [C.c_int32, C.c_int32, P]
+        L.kmco_get_partition.argtypes = [P, P, P]
         L.kmco_tick_slot.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32,
                                      C.c_int32, C.c_uint32, C.c_uint32, P]
         L.kmco_tick_slot.restype = C.c_uint32
@@ -94,6 +99,16 @@ def perm_from_index(idx):
     return p
 
 
+def schedule_index_n(seed, replica, sweep, n_perm):
+    return lib().kmco_schedule_index_n(seed, replica, sweep, n_perm)
+
+
+def perm_from_index_n(idx, n):
+    p = np.zeros(n, np.int32)
+    lib().kmco_perm_from_index_n(idx, n, _ptr(p))
+    return p
+
+
 def tick_slot(seed, replica, sweep, domain, visit, tick, n):
     r = C.c_int32(0)
     v = lib().kmco_tick_slot(seed, replica, sweep, domain, visit, tick, n,
@@ -106,12 +121,13 @@ class Replica:
 
     def __init__(self, L, tile, J=1.0, h=0.0, T=2.5, steps_per_visit=0,
                  rate_model=METROPOLIS, schedule=SCHED_RANDOM_PERM,
-                 init=INIT_RANDOM, seed=1, replica=0, spins=None):
+                 init=INIT_RANDOM, seed=1, replica=0, spins=None, tile_rows=0):
         self.desc = Desc(J, h, T, L, tile, steps_per_visit, rate_model,
-                         schedule, init)
+                         schedule, init, tile_rows)
         self.L, self.tile = L, tile
-        self.nd = tile * tile
-        self.ND = (L // tile) ** 2
+        self.tile_rows = tile_rows or tile
+        self.nd = tile * self.tile_rows
+        self.ND = (L // tile) * (L // self.tile_rows)
         self.NI = steps_per_visit or self.nd
         given = None
         if spins is not None:
@@ -149,6 +165,14 @@ class Replica:
         e = np.zeros(self.ND, np.int64)
         lib().kmco_get_domain_events(self._h, _ptr(e))
         return e
+
+    def partition(self):
+        """(colour of each domain, row-major over the domain grid; number of
+        colours)."""
+        col = np.zeros(self.ND, np.int32)
+        n = C.c_int32(0)
+        lib().kmco_get_partition(self._h, _ptr(col), C.byref(n))
+        return col, n.value
 
     def check_failures(self):
         return lib().kmco_check_failures(self._h)
