@@ -90,20 +90,27 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
 
-/* One replica.  Domain side `tile` = B: L % B == 0, 1 <= B <= 64 and L/B
- * even (a 4-colour checkerboard; the paper's Fig. 1 partition with
- * N_D = (L/B)^2), or L/B = 1 with B >= 3: the unpartitioned lattice as one
- * periodic domain (N_D = 1, the paper's reference dynamics).
- * steps_per_visit = N_I ticks per domain process (Sec. 2.2); 0 selects B*B
- * (one Monte Carlo step per site per visit). */
+/* One replica.  Domains are `tile` = Bx sites wide and `tile_rows` = By high
+ * (0: By = Bx), the paper's fixed equal partition (Sec. 2.2, Fig. 1):
+ * 1 <= Bx, By <= 64, L % Bx == 0, L % By == 0.  Square domains with L/B even
+ * give the 4-colour checkerboard, By = L gives vertical stripes, Bx = By = L
+ * the unpartitioned lattice as one periodic domain (N_D = 1, the paper's
+ * reference dynamics); odd domain counts are allowed too.  The domain grid is
+ * coloured per axis (1 colour for one domain, 2 for an even count, 3 for an
+ * odd count) and the schedule runs its colours in a uniformly drawn order
+ * (Eq. (schedule)) or as a palindrome.  An axis with a single domain wraps
+ * inside the domain and needs a side >= 3.  steps_per_visit = N_I ticks per
+ * domain process (Sec. 2.2); 0 selects Bx*By (one Monte Carlo step per site
+ * per visit). */
 typedef struct {
     double J, h, T;            /* coupling, field, k_B T (> 0)              */
     int32_t L;                 /* lattice side                              */
-    int32_t tile;              /* domain side B                             */
+    int32_t tile;              /* domain width Bx                           */
     int32_t steps_per_visit;   /* N_I, >= 0                                 */
     int32_t rate_model;        /* KMC_RATE_*                                */
     int32_t schedule;          /* KMC_SCHED_*                               */
     int32_t init;              /* KMC_INIT_*                                */
+    int32_t tile_rows;         /* domain height By; 0 means By = Bx         */
 } kmc_replica_desc;
 
 /* Observables at a sweep endpoint, the only points where statistics are

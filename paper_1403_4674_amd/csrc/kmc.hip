@@ -73,7 +73,7 @@ struct kmc_ctx {
     // per row-mask width (B <= 32, B > 32): some replica is one periodic
     // domain, so the launches of that width take the wrap-around kernels
     bool wrap[2] = {false, false};
-    int n_phase = 4;
+    int n_phase = 1;  // colour phases per sweep, the largest over the replicas
 
     Rep *d_reps = nullptr;
     Rates *d_rates = nullptr;
@@ -229,19 +229,45 @@ double sweep_cost(const Rep &rp, const kmc_replica_desc &d) {
     return (double)rp.NI * rp.ND * rp.visits * (1.0 + 6.0 * p);
 }
 
+// Domain height By (tile_rows 0: square domains).
+int tile_rows_of(const kmc_replica_desc &d) { return d.tile_rows ? d.tile_rows : d.tile; }
+
+// Colours along an axis of n domains (1, 2 for an even count, 3 for odd),
+// and the most domains any one colour holds on it.
+int axis_colours(int n) { return n == 1 ? 1 : (n % 2 ? 3 : 2); }
+int axis_most(int n) { return n == 1 ? 1 : n / 2; }
+
+// Domains of the largest colour class (phase tasks of the replica).
+int max_per_colour(const Rep &rp) { return axis_most(rp.NT) * axis_most(rp.NTy); }
+
+// Replicas the multi-slot kernel runs: square domains of at most 16 x 16 on a
+// 4-colour checkerboard.
+bool multi_ok(const Rep &rp) {
+    return rp.B <= 16 && rp.By == rp.B && rp.NT >= 2 && rp.NT % 2 == 0 && rp.NTy == rp.NT;
+}
+
+// Row masks of 64 bits (and 64-lane row scans) when a domain is wider or
+// taller than 32.
+bool wide(const Rep &rp) { return rp.B > 32 || rp.By > 32; }
+
 void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     auto bad = [&](const char *why) {
         fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": " + why);
     };
     if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
         bad("J, h must be finite and T > 0");
+    const int by = tile_rows_of(d);
     if (d.tile < 1 || d.tile > 64) bad("tile must be in [1, 64]");
+    if (by < 1 || by > 64) bad("tile_rows must be 0 or in [1, 64]");
     if (d.L < d.tile || d.L % d.tile) bad("L must be a multiple of tile");
+    if (d.L < by || d.L % by) bad("L must be a multiple of tile_rows");
     if (d.L == d.tile && d.tile < 3)
-        bad("a lattice that is one domain needs tile >= 3 (four distinct neighbours)");
-    if (d.L > d.tile && (d.L / d.tile) % 2)
-        bad("L/tile must be 1 or even (4-colour checkerboard)");
-    if ((int64_t)(d.L / d.tile) * (d.L / d.tile) > (1 << 20)) bad("more than 2^20 domains");
+        bad("a domain as wide as the lattice needs tile >= 3 (distinct left and right "
+            "neighbours)");
+    if (d.L == by && by < 3)
+        bad("a domain as high as the lattice needs tile_rows >= 3 (distinct up and down "
+            "neighbours)");
+    if ((int64_t)(d.L / d.tile) * (d.L / by) > (1 << 20)) bad("more than 2^20 domains");
     if (d.steps_per_visit < 0) bad("steps_per_visit must be >= 0");
     if (d.rate_model != KMC_RATE_METROPOLIS && d.rate_model != KMC_RATE_BARKER)
         bad("unknown rate model");
@@ -572,11 +598,17 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             Rep &rp = c->reps[rho];
             rp.L = q.L;
             rp.B = q.tile;
+            rp.By = tile_rows_of(q);
             rp.NT = q.L / q.tile;
-            rp.NI = q.steps_per_visit ? q.steps_per_visit : q.tile * q.tile;
+            rp.NTy = q.L / rp.By;
+            rp.cx = axis_colours(rp.NT);
+            rp.ncol = rp.cx * axis_colours(rp.NTy);
+            rp.nperm = 1;
+            for (int k = 2; k <= rp.ncol; ++k) rp.nperm *= k;
+            rp.NI = q.steps_per_visit ? q.steps_per_visit : q.tile * rp.By;
             rp.sched = q.schedule;
-            rp.ND = rp.NT * rp.NT;
-            rp.nd = (uint32_t)(q.tile * q.tile);
+            rp.ND = rp.NT * rp.NTy;
+            rp.nd = (uint32_t)(q.tile * rp.By);
             rp.thr = (uint32_t)(0u - rp.nd) % rp.nd;
             rp.spin_off = off;
             off += (bytes_of_spins(q) + 255) / 256 * 256;
@@ -584,7 +616,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             dom += rp.ND;
             rp.visits = q.schedule == KMC_SCHED_PALINDROME ? 2 : 1;
             rp.init = q.init;
-            if (q.schedule == KMC_SCHED_PALINDROME) c->n_phase = 8;
+            c->n_phase = std::max(c->n_phase,
+                                  (q.schedule == KMC_SCHED_PALINDROME ? 2 : 1) * rp.ncol);
             if (q.init == KMC_INIT_GIVEN) any_given = true;
             Rates &R = c->rates[rho];
             std::memset(&R, 0, sizeof(R));
@@ -604,15 +637,17 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         c->spin_bytes = off;
         c->n_dom = dom;
 
-        // phase tasks: replicas with B <= 32 first (32-bit row masks)
+        // phase tasks (as many per replica as its largest colour class has
+        // domains): replicas with domains of at most 32 x 32 first (32-bit
+        // row masks)
         std::vector<int32_t> task_rep;
         for (int pass = 0; pass < 2; ++pass)
             for (int rho = 0; rho < n_rep; ++rho) {
                 Rep &rp = c->reps[rho];
-                if ((rp.B > 32) != (pass == 1)) continue;
-                if (rp.NT == 1) c->wrap[pass] = true;
+                if (wide(rp) != (pass == 1)) continue;
+                if (rp.NT == 1 || rp.NTy == 1) c->wrap[pass] = true;
                 rp.task_off = (int32_t)task_rep.size();
-                for (int i = 0; i < std::max(rp.ND / 4, 1); ++i) task_rep.push_back(rho);
+                for (int i = 0; i < max_per_colour(rp); ++i) task_rep.push_back(rho);
                 if (pass == 0) c->n_tasks32 = (int32_t)task_rep.size();
             }
         c->n_tasks = (int32_t)task_rep.size();
@@ -639,7 +674,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         };
         std::vector<int32_t> mrep;  // multi-slot candidates
         for (int rho = 0; rho < n_rep; ++rho)
-            if (c->reps[rho].B <= 16 && c->reps[rho].NT >= 2) mrep.push_back(rho);
+            if (multi_ok(c->reps[rho])) mrep.push_back(rho);
         {
             std::stable_sort(mrep.begin(), mrep.end(), by_cost);
             std::vector<MItem> wg, wv;
@@ -687,10 +722,10 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                 std::vector<int32_t> team, solo;
                 for (int rho = 0; rho < n_rep; ++rho) {
                     const Rep &rp = c->reps[rho];
-                    if ((rp.B > 32) != (pass == 1)) continue;
-                    if (use_multi && rp.B <= 16) continue;
+                    if (wide(rp) != (pass == 1)) continue;
+                    if (use_multi && multi_ok(rp)) continue;
                     const int64_t ticks = (int64_t)rp.NI * rp.ND * rp.visits;
-                    const bool split = rp.ND / 4 >= 4 && (ticks >= 8192 || few);
+                    const bool split = max_per_colour(rp) >= 4 && (ticks >= 8192 || few);
                     (split ? team : solo).push_back(rho);
                 }
                 std::stable_sort(team.begin(), team.end(), by_cost);

@@ -55,7 +55,10 @@ struct Rates {
 };
 
 struct Rep {
-    int32_t L, B, NT, NI;   // lattice side, domain side, L/B, ticks per visit
+    int32_t L, B, NT, NI;   // lattice side, domain width Bx, L/Bx, ticks per visit
+    int32_t By, NTy;        // domain height, L/By
+    int32_t ncol, cx;       // colours of the domain grid, colours along x
+    int32_t nperm;          // ncol! (orders of the random schedule)
     int32_t sched, ND;      // schedule kind, number of domains
     uint32_t nd, thr;       // sites per domain, 2^32 mod nd
     int64_t spin_off;       // byte offset of the lattice
@@ -134,56 +137,83 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
     return make_uint4(c0, c1, c2, c3);
 }
 
-// Uniform index in [0, 24) of the colour order of (replica, sweep).
-__device__ inline int schedule_index(uint64_t seed, uint32_t rho, uint32_t w) {
+// Uniform index in [0, n) of the colour order of (replica, sweep), n = ncol!:
+// Lemire multiply-high with rejection of the 2^32 mod n smallest low halves.
+__device__ inline int schedule_index(uint64_t seed, uint32_t rho, uint32_t w, uint32_t n) {
+    const uint32_t thr = (0u - n) % n;  // 2^32 mod n
     for (uint32_t call = 0;; ++call) {
         const uint4 o = philox(call, kStreamSched << 24, w, rho, (uint32_t)seed,
                                (uint32_t)(seed >> 32));
         const uint32_t v[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint64_t m = (uint64_t)v[i] * 24u;
-            if ((uint32_t)m >= 16u) return (int)(m >> 32);
+            const uint64_t m = (uint64_t)v[i] * n;
+            if ((uint32_t)m >= thr) return (int)(m >> 32);
         }
     }
 }
 
-// Element p of the permutation of {0,1,2,3} with lexicographic rank idx.
-__device__ inline int perm_element(int idx, int p) {
-    int avail = 0xF;  // bit set = colour still available
-    const int radix[3] = {6, 2, 1};
-    int out = 0;
-    for (int i = 0; i <= p && i < 4; ++i) {
-        int a = i < 3 ? idx / radix[i] : 0;
-        if (i < 3) idx %= radix[i];
-        int pick = -1;
-        for (int c = 0; c < 4; ++c) {
-            if (avail & (1 << c)) {
-                if (a == 0) {
-                    pick = c;
-                    break;
-                }
-                --a;
-            }
-        }
-        avail &= ~(1 << pick);
-        out = pick;
+// Positions of the permutation of {0..n-1} (n <= 9) with lexicographic rank
+// idx, as 4-bit fields: field e holds the position of element e.  Digit i of
+// the rank in the factorial number system picks among the unused values.
+__device__ inline uint64_t perm_positions(int idx, int n) {
+    int f = 1;  // (n - 1)!
+    for (int k = 2; k < n; ++k) f *= k;
+    uint32_t avail = (1u << n) - 1u;
+    uint64_t pos = 0;
+    for (int i = 0; i < n; ++i) {
+        const int a = idx / f;
+        idx -= a * f;
+        if (n - 1 - i > 0) f /= n - 1 - i;
+        uint32_t m = avail;
+        for (int k = 0; k < a; ++k) m &= m - 1u;  // drop the a smallest
+        const int pick = __builtin_ctz(m);
+        avail &= ~(1u << pick);
+        pos |= (uint64_t)i << (4 * pick);
     }
-    return out;
+    return pos;
 }
 
-// Colour and visit index of phase p of sweep w (phase p < 4 for the random
-// order, p < 8 for the palindrome ABCDDCBA); -1 when the phase is empty.
+// Element at position p of that permutation.
+__device__ inline int perm_element(int idx, int p, int n) {
+    const uint64_t pos = perm_positions(idx, n);
+    for (int e = 0; e < n; ++e)
+        if ((int)((pos >> (4 * e)) & 15u) == p) return e;
+    return -1;
+}
+
+// Colouring of the domain grid, per axis of n domains: one colour for a
+// single domain, t mod 2 for an even count, t mod 2 with the last domain
+// given colour 2 for an odd count (an odd cycle needs three colours).  The
+// colour of domain (ty, tx) is ax + cx ay; domains of one colour never share
+// an edge, so they commute (Sec. 2.2).
+__device__ __forceinline__ int axis_colour(int t, int n) {
+    return n == 1 ? 0 : ((n & 1) && t == n - 1) ? 2 : (t & 1);
+}
+// Number of domains of axis colour a, and the position of the i-th of them.
+__device__ __forceinline__ int axis_count(int a, int n) {
+    return n == 1 ? (a == 0 ? 1 : 0) : (n & 1) ? (a == 2 ? 1 : (n - 1) >> 1) : (a < 2 ? n >> 1 : 0);
+}
+__device__ __forceinline__ int axis_pos(int i, int a, int n) {
+    return ((n & 1) && a == 2) ? n - 1 : 2 * i + a;
+}
+__device__ __forceinline__ int dom_colour(const Rep &rp, int ty, int tx) {
+    return axis_colour(tx, rp.NT) + rp.cx * axis_colour(ty, rp.NTy);
+}
+
+// Colour and visit index of phase p of sweep w (p < ncol for the random
+// order, p < 2 ncol for the palindrome); -1 when the phase is empty.
 __device__ inline int phase_colour(const Rep &rp, uint64_t seed, uint32_t rho,
                                    uint32_t w, int p, int *visit) {
-    if (rp.sched == 1) {
-        const int pal = p < 4 ? p : 7 - p;
-        *visit = p < 4 ? 0 : 1;
-        return pal;
+    const int n = rp.ncol;
+    if (rp.sched == 1) {  // 0 1 .. n-1 n-1 .. 1 0, second visits on the way back
+        *visit = p < n ? 0 : 1;
+        if (p >= 2 * n) return -1;
+        return p < n ? p : 2 * n - 1 - p;
     }
     *visit = 0;
-    if (p >= 4) return -1;
-    return perm_element(schedule_index(seed, rho, w), p);
+    if (p >= n) return -1;
+    return perm_element(schedule_index(seed, rho, w, (uint32_t)rp.nperm), p, n);
 }
 
 // ------------------------------------------------------------ wave helpers
@@ -404,14 +434,14 @@ struct Planes {
 
 template <typename MT>
 __device__ __forceinline__ Planes<MT> neighbour_planes(MT S, MT top, MT bot,
-                                                      MT hl, MT hr, int B,
+                                                      MT hl, MT hr, int Bx, int By,
                                                       MT VM, int lane) {
     MT U = dpp_any<kWaveShr1>(S);
     if (lane == 0) U = top;
     MT D = dpp_any<kWaveShl1>(S);
-    if (lane == B - 1) D = bot;
+    if (lane == By - 1) D = bot;
     const MT Lf = ((S << 1) | hl) & VM;
-    const MT Rt = ((S >> 1) | (hr << (B - 1))) & VM;
+    const MT Rt = ((S >> 1) | (hr << (Bx - 1))) & VM;
     U &= VM;
     D &= VM;
     const MT p1 = U ^ D, q1 = U & D;
@@ -559,18 +589,19 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                                  uint32_t rho, uint64_t seed, Dom *dom,
                                  uint8_t *lds) {
     const int lane = __lane_id();
-    const int L = rp.L, B = rp.B, NI = rp.NI;
+    // B: row width (bits of a row mask), By: rows (lanes)
+    const int L = rp.L, B = rp.B, By = rp.By, NI = rp.NI;
     const int B4 = B >> 2;
     const uint32_t nd = rp.nd, thr = rp.thr;
 
     // ---- stage the tile and the top/bottom halo rows through LDS.  LDS rows
-    // are padded to whole dwords (stride SB); sides that are multiples of 4
-    // move as dwords, other sides byte by byte.
+    // are padded to whole dwords (stride SB); widths that are multiples of 4
+    // move as dwords, other widths byte by byte.
     const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds;
     uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
     if ((B & 3) == 0) {
-        for (int q = lane; q < B * B4; q += 64) {
+        for (int q = lane; q < By * B4; q += 64) {
             const int row = q / B4, c4 = q - row * B4;
             const uint32_t v = *reinterpret_cast<const uint32_t *>(
                 lat + (int64_t)(oy + row) * L + ox + 4 * c4);
@@ -578,24 +609,24 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         }
         if (lane < 2 * B4) {
             const int which = lane / B4, c4 = lane - which * B4;
-            const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
+            const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
             const uint32_t v =
                 *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + ox + 4 * c4);
             *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) = v;
         }
     } else {
-        for (int q = lane; q < B * B; q += 64) {
+        for (int q = lane; q < By * B; q += 64) {
             const int row = q / B, col = q - row * B;
             tile[row * SB + col] = (uint8_t)lat[(int64_t)(oy + row) * L + ox + col];
         }
         for (int q = lane; q < 2 * B; q += 64) {
             const int which = q / B, col = q - which * B;
-            const int y = which ? (oy + B) % L : (oy - 1 + L) % L;
+            const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
             hrow[which * 64 + col] = (uint8_t)lat[(int64_t)y * L + ox + col];
         }
     }
     MT hl = 0, hr = 0;
-    if (lane < B) {
+    if (lane < By) {
         const int64_t rowbase = (int64_t)(oy + lane) * L;
         hl = lat[rowbase + (ox - 1 + L) % L] > 0 ? 1 : 0;
         hr = lat[rowbase + (ox + B) % L] > 0 ? 1 : 0;
@@ -603,10 +634,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     wave_sync_lds();
 
     const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
-    const MT VM = lane < B ? vm_row : (MT)0;
+    const MT VM = lane < By ? vm_row : (MT)0;
     MT S = 0, top = 0, bot = 0;
     for (int q = 0; q < SB4; ++q) {
-        if (lane < B)
+        if (lane < By)
             S |= (MT)bytes_to_bits(
                      *reinterpret_cast<const uint32_t *>(tile + lane * SB + 4 * q))
                  << (4 * q);
@@ -618,7 +649,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     S &= VM;  // padding bytes decode to set bits: clear them
     top &= vm_row;
     bot &= vm_row;
-    Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, VM, lane);
+    Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, By, VM, lane);
 
     // ---- class counts: per-row popcounts, two classes per 32-bit word
     uint32_t n_lane = 0;  // lanes 0..9: n_c
@@ -650,9 +681,11 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     uint32_t m_null = 0;                   // null ticks since the last event (score)
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = d | (vis << 20) | (kStreamTick << 24);
-    // a lattice that is one domain is periodic in itself: its boundary
-    // neighbours are its own sites and change during the visit
-    const int wrapB = WRAP && rp.NT == 1 ? B : 0;
+    // along an axis with a single domain (one domain, or a stripe) the
+    // domain is periodic in itself: its boundary neighbours on that axis are
+    // its own sites and change during the visit
+    const int wrapY = WRAP && rp.NTy == 1 ? By : 0;
+    const int wrapX = WRAP && rp.NT == 1 ? B : 0;
 
     // Score.  A run of m null ticks adds m d ln(1 - R_w/n_d)/d theta =
     // -m sum_c n_c a_c / (n_d - R_w) (a_c = w_c d ln w_c/d theta), linear in
@@ -738,10 +771,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             // halo and frozen, unless the lattice is one periodic domain
             const bool up = c >= 5;
             const int c_new = up ? c - 5 : c + 5;
-            const int ym = ys - 1 + (ys == 0 ? wrapB : 0), yp = ys + 1 - (ys == B - 1 ? wrapB : 0);
-            const int xm = xs - 1 + (xs == 0 ? wrapB : 0), xp = xs + 1 - (xs == B - 1 ? wrapB : 0);
+            const int ym = ys - 1 + (ys == 0 ? wrapY : 0), yp = ys + 1 - (ys == By - 1 ? wrapY : 0);
+            const int xm = xs - 1 + (xs == 0 ? wrapX : 0), xp = xs + 1 - (xs == B - 1 ? wrapX : 0);
             const bool on_row = lane == ys;
-            const bool adj = (lane == ym || lane == yp) && lane < B;
+            const bool adj = (lane == ym || lane == yp) && lane < By;
             constexpr int NB = 8 * (int)sizeof(MT);
             const int ca = on_row ? xm : xs;
             const bool va = on_row ? xm >= 0 : adj;
@@ -750,7 +783,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
             uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
             uint32_t nb_s;
-            if (wrapB == 0) {
+            if (wrapY == 0) {  // rows ys -/+ 1 are the neighbouring lanes
                 nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
                 nb_s = rdl32(nb, ys);
             } else {
@@ -819,20 +852,20 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     }
 
     // ---- write the tile back through LDS
-    if (lane < B) {
+    if (lane < By) {
         for (int q = 0; q < SB4; ++q)
             *reinterpret_cast<uint32_t *>(tile + lane * SB + 4 * q) =
                 bits_to_bytes((uint32_t)(S >> (4 * q)) & 0xFu);
     }
     wave_sync_lds();
     if ((B & 3) == 0) {
-        for (int q = lane; q < B * B4; q += 64) {
+        for (int q = lane; q < By * B4; q += 64) {
             const int row = q / B4, c4 = q - row * B4;
             *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
                 *reinterpret_cast<const uint32_t *>(tile + row * SB + 4 * c4);
         }
     } else {
-        for (int q = lane; q < B * B; q += 64) {
+        for (int q = lane; q < By * B; q += 64) {
             const int row = q / B, col = q - row * B;
             lat[(int64_t)(oy + row) * L + ox + col] = (int8_t)tile[row * SB + col];
         }
@@ -841,26 +874,21 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     return out;
 }
 
-// Number of domains of colour `col`: N_D / 4, or, for a lattice that is a
-// single domain (N_D = 1, periodic in itself), 1 for colour 0 and 0 otherwise.
+// Number of domains of colour `col` (N_D / 4 on a 4-colour checkerboard).
 __device__ __forceinline__ int domains_of_colour(const Rep &rp, int col) {
-    return rp.NT == 1 ? (col == 0 ? 1 : 0) : rp.ND >> 2;
+    if (col < 0 || col >= rp.ncol) return 0;
+    return axis_count(col % rp.cx, rp.NT) * axis_count(col / rp.cx, rp.NTy);
 }
 
-// Origin of the i-th domain of colour `col` (ascending domain index).
+// Index and origin of the i-th domain of colour `col` (ascending index).
 __device__ __forceinline__ void colour_domain(const Rep &rp, int col, int i,
                                               int *d, int *oy, int *ox) {
-    if (rp.NT == 1) {
-        *d = 0;
-        *oy = 0;
-        *ox = 0;
-        return;
-    }
-    const int half = rp.NT >> 1;
-    const int tx = 2 * (i % half) + (col & 1);
-    const int ty = 2 * (i / half) + (col >> 1);
+    const int ax = col % rp.cx, ay = col / rp.cx;
+    const int nx = axis_count(ax, rp.NT);
+    const int tx = axis_pos(i % nx, ax, rp.NT);
+    const int ty = axis_pos(i / nx, ay, rp.NTy);
     *d = ty * rp.NT + tx;
-    *oy = ty * rp.B;
+    *oy = ty * rp.By;
     *ox = tx * rp.B;
 }
 
@@ -912,10 +940,10 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
 // End of a sweep: one wavefront per replica writes the record when due.
 // Number of visits of colour `col` at positions before p in the sweep's
 // schedule (random order: one visit per sweep, at the position held in the
-// 2-bit field col of pos_of; palindrome ABCDDCBA: two).
-__device__ inline int visits_before(const Rep &rp, uint32_t pos_of, int col, int p) {
-    if (rp.sched == 1) return (col < p ? 1 : 0) + (7 - col < p ? 1 : 0);
-    return (int)((pos_of >> (2 * col)) & 3u) < p ? 1 : 0;
+// 4-bit field col of pos_of; palindrome 0 1 .. n-1 n-1 .. 1 0: two).
+__device__ inline int visits_before(const Rep &rp, uint64_t pos_of, int col, int p) {
+    if (rp.sched == 1) return (col < p ? 1 : 0) + (2 * rp.ncol - 1 - col < p ? 1 : 0);
+    return (int)((pos_of >> (4 * col)) & 15u) < p ? 1 : 0;
 }
 
 constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;
@@ -949,15 +977,13 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
     int64_t *dn = done + rp.dom_off;
     const int64_t base = 4 * (int64_t)w;
     if (__lane_id() == 0) {
-        uint32_t pos_of = 0;  // 2-bit position of each colour in this sweep's order
-        if (rp.sched != 1) {
-            const int idx = schedule_index(K.seed, (uint32_t)rho, w);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pos_of |= (uint32_t)q << (2 * perm_element(idx, q));
-        }
-        const int NT = rp.NT, ty = d / NT, tx = d - ty * NT;
+        uint64_t pos_of = 0;  // 4-bit position of each colour in this sweep's order
+        if (rp.sched != 1)
+            pos_of = perm_positions(
+                schedule_index(K.seed, (uint32_t)rho, w, (uint32_t)rp.nperm), rp.ncol);
+        const int NT = rp.NT, NTy = rp.NTy, ty = d / NT, tx = d - ty * NT;
         auto wait_for = [&](int ey, int ex) {
-            const int need = visits_before(rp, pos_of, 2 * (ey & 1) + (ex & 1), p);
+            const int need = visits_before(rp, pos_of, dom_colour(rp, ey, ex), p);
             if (need == 0) return;
             const int64_t *cnt = dn + ey * NT + ex;
             int64_t polls = 0;
@@ -971,8 +997,8 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
                 }
             }
         };
-        wait_for((ty + NT - 1) % NT, tx);
-        wait_for((ty + 1) % NT, tx);
+        wait_for((ty + NTy - 1) % NTy, tx);
+        wait_for((ty + 1) % NTy, tx);
         wait_for(ty, (tx + NT - 1) % NT);
         wait_for(ty, (tx + 1) % NT);
         wait_for(ty, tx);  // the palindrome's second visit waits for the first
@@ -1097,7 +1123,7 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
     RepAcc acc = K.acc[rho];  // with a team, wavefront 0 keeps the totals
     int64_t dM = 0, dB = 0, ev = 0;
     double sJ = 0.0, sh = 0.0;
-    const int nphase = rp.sched == 1 ? 8 : 4;
+    const int nphase = (rp.sched == 1 ? 2 : 1) * rp.ncol;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const uint32_t w = (uint32_t)(sweep0 + i);
         for (int p = 0; p < nphase; ++p) {

@@ -36,7 +36,8 @@ class KmcError(RuntimeError):
 class ReplicaDesc(C.Structure):
     _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
                 ("L", C.c_int32), ("tile", C.c_int32), ("steps_per_visit", C.c_int32),
-                ("rate_model", C.c_int32), ("schedule", C.c_int32), ("init", C.c_int32)]
+                ("rate_model", C.c_int32), ("schedule", C.c_int32), ("init", C.c_int32),
+                ("tile_rows", C.c_int32)]
 
 
 RECORD_DTYPE = np.dtype([("sweep", "<i8"), ("M", "<i8"), ("B", "<i8"),
@@ -137,13 +138,15 @@ def make_descs(descs):
                              int(d.get("steps_per_visit", 0)),
                              int(d.get("rate_model", RATE_METROPOLIS)),
                              int(d.get("schedule", SCHED_RANDOM_PERM)),
-                             int(d.get("init", INIT_RANDOM)))
+                             int(d.get("init", INIT_RANDOM)),
+                             int(d.get("tile_rows", 0)))
     return arr
 
 
 def kmc_init_lattice(descs, seed, given_spins=None, stream=None):
     """descs: list of dicts with keys L, tile, T and optional J, h,
-    steps_per_visit, rate_model, schedule, init.  stream: a hipStream_t
+    steps_per_visit, rate_model, schedule, init, tile_rows (domain height;
+    0 or absent: square domains).  stream: a hipStream_t
     handle (int) or None for torch's current stream.  Returns the context."""
     arr = make_descs(descs)
     if stream is None:

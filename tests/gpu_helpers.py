@@ -14,7 +14,8 @@ def oracle_for(kmco, desc, seed, rho, spins=None):
                         T=desc["T"], steps_per_visit=desc.get("steps_per_visit", 0),
                         rate_model=desc.get("rate_model", 0),
                         schedule=desc.get("schedule", 0), init=desc.get("init", 0),
-                        seed=seed, replica=rho, spins=spins)
+                        seed=seed, replica=rho, spins=spins,
+                        tile_rows=desc.get("tile_rows", 0))
 
 
 def assert_records_equal(gpu, ora, what=""):

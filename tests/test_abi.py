@@ -61,9 +61,12 @@ def test_rate_table_rejects_bad_input(kmc):
 
 BAD = [
     dict(L=16, tile=6, T=2.0),    # L not a multiple of tile
-    dict(L=24, tile=8, T=2.0),    # L/tile odd
-    dict(L=15, tile=5, T=2.0),    # L/tile odd
     dict(L=2, tile=2, T=2.0),     # one domain with fewer than three rows
+    dict(L=12, tile=4, tile_rows=5, T=2.0),    # L not a multiple of tile_rows
+    dict(L=16, tile=8, tile_rows=-1, T=2.0),   # tile_rows below 0
+    dict(L=128, tile=16, tile_rows=128, T=2.0),  # tile_rows above 64
+    dict(L=2, tile=1, tile_rows=2, T=2.0),     # wrapped column with two sites
+    dict(L=2, tile=2, tile_rows=1, T=2.0),     # wrapped row with two sites
     dict(L=8, tile=0, T=2.0),     # tile below 1
     dict(L=20, tile=8, T=2.0),    # L not a multiple of tile
     dict(L=256, tile=128, T=2.0), # tile above 64

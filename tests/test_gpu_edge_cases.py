@@ -100,14 +100,29 @@ SHAPES = {
     "single12": dict(L=12, tile=12, T=2.4, rate_model=kmc.RATE_BARKER),
     "single16_palin": dict(L=16, tile=16, T=2.1, h=0.2, schedule=kmc.SCHED_PALINDROME),
     "single40": dict(L=40, tile=40, T=2.5, steps_per_visit=700),   # 64-bit rows
+    # general partitions: vertical stripes (wrap in y), odd domain counts
+    # (3 colours per axis), rectangles, horizontal stripes (wrap in x)
+    "stripes2": dict(L=12, tile=6, tile_rows=12, T=2.4, rate_model=kmc.RATE_BARKER),
+    "stripes4": dict(L=12, tile=3, tile_rows=12, T=2.4, rate_model=kmc.RATE_BARKER,
+                     steps_per_visit=10),
+    "stripes5_palin": dict(L=20, tile=4, tile_rows=20, T=2.2, h=0.1,
+                           schedule=kmc.SCHED_PALINDROME),
+    "odd3x3": dict(L=12, tile=4, T=2.3),                 # 9 colours
+    "odd3x3_palin": dict(L=15, tile=5, T=2.0, schedule=kmc.SCHED_PALINDROME),
+    "rect8x4": dict(L=16, tile=8, tile_rows=4, T=2.5, h=-0.1),
+    "rect3x5": dict(L=15, tile=3, tile_rows=5, T=2.6, steps_per_visit=40),
+    "hstripes": dict(L=12, tile=12, tile_rows=6, T=2.4),
+    "tall48": dict(L=48, tile=16, tile_rows=48, T=2.3, steps_per_visit=500),  # 48 rows
+    "wide64x8": dict(L=64, tile=64, tile_rows=8, T=2.7, steps_per_visit=600),
 }
 
 
 @pytest.mark.parametrize("form", ["phased", "flow", "persistent"])
 @pytest.mark.parametrize("case", list(SHAPES))
 def test_domain_shapes_match_oracle(torch_cuda, oracle_lib, case, form):
-    """Domain sides that are not multiples of 4 (byte-wise staging) and the
-    unpartitioned lattice as one periodic domain, in every execution form."""
+    """Domain sides that are not multiples of 4 (byte-wise staging), the
+    unpartitioned lattice as one periodic domain, stripes, odd domain counts
+    and rectangular domains, in every execution form."""
     d = SHAPES[case]
     flags = {"phased": 0, "flow": kmc.F_FLOW, "persistent": kmc.F_PERSISTENT | kmc.F_MULTI}[form]
     say(f"shape {case}, {form}")
