@@ -117,12 +117,13 @@ def observable(records, L, J=1.0, h=0.0, kind="H"):
 
 
 def run_setting(kmc, L, tile, steps_per_visit, T, n_traj, n_sweeps, record_every, seed,
-                J=1.0, h=0.0, rate_model=1, init_spins=None, flags=None):
+                J=1.0, h=0.0, rate_model=1, init_spins=None, flags=None, tile_rows=0):
     """n_traj trajectories of one parallelisation setting on the GPU (one
-    batched persistent launch).  Returns records [n_traj, n_records]; with a
-    given start configuration a first column holds the start state (s = 0)."""
+    batched persistent launch; domains `tile` wide and `tile_rows` high).
+    Returns records [n_traj, n_records]; with a given start configuration a
+    first column holds the start state (s = 0)."""
     d = dict(L=L, tile=tile, T=T, J=J, h=h, steps_per_visit=steps_per_visit,
-             rate_model=rate_model)
+             rate_model=rate_model, tile_rows=tile_rows)
     given = None
     if init_spins is not None:
         d["init"] = kmc.INIT_GIVEN

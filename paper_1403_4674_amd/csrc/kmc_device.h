@@ -153,18 +153,21 @@ __device__ inline int schedule_index(uint64_t seed, uint32_t rho, uint32_t w, ui
     }
 }
 
-// Positions of the permutation of {0..n-1} (n <= 9) with lexicographic rank
-// idx, as 4-bit fields: field e holds the position of element e.  Digit i of
-// the rank in the factorial number system picks among the unused values.
-__device__ inline uint64_t perm_positions(int idx, int n) {
-    int f = 1;  // (n - 1)!
-    for (int k = 2; k < n; ++k) f *= k;
-    uint32_t avail = (1u << n) - 1u;
+// Positions of the permutation of {0..N-1} with lexicographic rank idx, as
+// 4-bit fields: field e holds the position of element e.  Digit i of the
+// rank in the factorial number system (radix (N-1-i)!, a constant once the
+// loop is unrolled) picks among the unused values.
+constexpr int cfact(int n) { return n <= 1 ? 1 : n * cfact(n - 1); }
+
+template <int N>
+__device__ __forceinline__ uint64_t perm_positions_n(int idx) {
+    uint32_t avail = (1u << N) - 1u;
     uint64_t pos = 0;
-    for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int f = cfact(N - 1 - i);
         const int a = idx / f;
         idx -= a * f;
-        if (n - 1 - i > 0) f /= n - 1 - i;
         uint32_t m = avail;
         for (int k = 0; k < a; ++k) m &= m - 1u;  // drop the a smallest
         const int pick = __builtin_ctz(m);
@@ -174,12 +177,25 @@ __device__ inline uint64_t perm_positions(int idx, int n) {
     return pos;
 }
 
+// The colour counts a grid can have: 1, 2, 3 colours per axis.
+__device__ inline uint64_t perm_positions(int idx, int n) {
+    switch (n) {
+    case 2: return perm_positions_n<2>(idx);
+    case 3: return perm_positions_n<3>(idx);
+    case 4: return perm_positions_n<4>(idx);
+    case 6: return perm_positions_n<6>(idx);
+    case 9: return perm_positions_n<9>(idx);
+    default: return 0;  // one colour
+    }
+}
+
 // Element at position p of that permutation.
 __device__ inline int perm_element(int idx, int p, int n) {
     const uint64_t pos = perm_positions(idx, n);
+    int out = 0;
     for (int e = 0; e < n; ++e)
-        if ((int)((pos >> (4 * e)) & 15u) == p) return e;
-    return -1;
+        if ((int)((pos >> (4 * e)) & 15u) == p) out = e;
+    return out;
 }
 
 // Colouring of the domain grid, per axis of n domains: one colour for a
@@ -200,6 +216,12 @@ __device__ __forceinline__ int axis_pos(int i, int a, int n) {
 __device__ __forceinline__ int dom_colour(const Rep &rp, int ty, int tx) {
     return axis_colour(tx, rp.NT) + rp.cx * axis_colour(ty, rp.NTy);
 }
+// Axis colours (ax, ay) of colour col (cx is 1, 2 or 3; col < 9).
+__device__ __forceinline__ void split_colour(const Rep &rp, int col, int *ax, int *ay) {
+    const int y = rp.cx == 2 ? col >> 1 : rp.cx == 1 ? col : (col * 11) >> 5;  // col / 3
+    *ay = y;
+    *ax = col - rp.cx * y;
+}
 
 // Colour and visit index of phase p of sweep w (p < ncol for the random
 // order, p < 2 ncol for the palindrome); -1 when the phase is empty.
@@ -214,6 +236,24 @@ __device__ inline int phase_colour(const Rep &rp, uint64_t seed, uint32_t rho,
     *visit = 0;
     if (p >= n) return -1;
     return perm_element(schedule_index(seed, rho, w, (uint32_t)rp.nperm), p, n);
+}
+
+// phase_colour for a replica known to be a 4-colour checkerboard (the
+// multi-slot kernel's replicas): the same colours and visits.
+__device__ inline int phase_colour4(uint32_t sched, uint64_t seed, uint32_t rho, uint32_t w,
+                                    int p, int *visit) {
+    if (sched == 1) {
+        *visit = p < 4 ? 0 : 1;
+        return p < 8 ? (p < 4 ? p : 7 - p) : -1;
+    }
+    *visit = 0;
+    if (p >= 4) return -1;
+    const uint64_t pos = perm_positions_n<4>(schedule_index(seed, rho, w, 24u));
+    int out = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if ((int)((pos >> (4 * e)) & 15u) == p) out = e;
+    return out;
 }
 
 // ------------------------------------------------------------ wave helpers
@@ -877,13 +917,16 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
 // Number of domains of colour `col` (N_D / 4 on a 4-colour checkerboard).
 __device__ __forceinline__ int domains_of_colour(const Rep &rp, int col) {
     if (col < 0 || col >= rp.ncol) return 0;
-    return axis_count(col % rp.cx, rp.NT) * axis_count(col / rp.cx, rp.NTy);
+    int ax, ay;
+    split_colour(rp, col, &ax, &ay);
+    return axis_count(ax, rp.NT) * axis_count(ay, rp.NTy);
 }
 
 // Index and origin of the i-th domain of colour `col` (ascending index).
 __device__ __forceinline__ void colour_domain(const Rep &rp, int col, int i,
                                               int *d, int *oy, int *ox) {
-    const int ax = col % rp.cx, ay = col / rp.cx;
+    int ax, ay;
+    split_colour(rp, col, &ax, &ay);
     const int nx = axis_count(ax, rp.NT);
     const int tx = axis_pos(i % nx, ax, rp.NT);
     const int ty = axis_pos(i / nx, ay, rp.NTy);

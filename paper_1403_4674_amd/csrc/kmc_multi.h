@@ -416,7 +416,7 @@ __device__ void run_item(const KParams &K, const MItem &it, int wave, int lane, 
         const uint32_t w = (uint32_t)(sweep0 + i);
         for (int p = 0; p < nphase; ++p) {
             int vis = 0;
-            const int col = on_rep ? phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis) : 0;
+            const int col = on_rep ? phase_colour4((uint32_t)rp.sched, K.seed, (uint32_t)rho, w, p, &vis) : 0;
             for (int kk = 0; kk < steps; ++kk) {
                 const int i2 = intra ? g + kk * stride : kk;
                 SlotDomain A;

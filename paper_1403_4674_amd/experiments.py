@@ -1,9 +1,10 @@
 """The paper's 2D parallelisation study, run on the GPU (Sec. 3.2, Table 1,
 Fig. (full-summary)): a periodic Ising lattice at k_B T / J = 2.4 with
 Glauber (Barker) rates, started from the filled circle, evolved with no
-partition (the reference, N_D = 1) and with checkerboard partitions for
-several N_I; each setting is a batch of independent trajectories in one
-persistent launch.  The analysis (tau, eta, chi^2) is `analysis.py`.
+partition (the reference, N_D = 1), with vertical stripes (N_D = 2, 4) and
+with checkerboards (N_D = 4, 16) for N_I in {1, 2, 5, 10}; each setting is a
+batch of independent trajectories in one persistent launch.  The analysis
+(tau, eta, chi^2) is `analysis.py`.
 
     python -m paper_1403_4674_amd.experiments --L 12 --traj 500
 
@@ -19,15 +20,18 @@ from . import analysis
 
 
 def settings_2d(L):
-    """(label, tile, N_I) of the unpartitioned reference and the checkerboard
-    settings with 4 domains (and 16 when L/4 is a valid tile)."""
-    out = [("reference", L, L * L)]
-    for nd_side in (2, 4):
-        B = L // nd_side
-        if L % nd_side or B < 1:
+    """(label, domain width, domain height, N_I) of the unpartitioned
+    reference, vertical stripes with N_D = 2 and 4, and checkerboards with
+    N_D = 4 and 16, each for N_I in {1, 2, 5, 10} (partitions that do not
+    divide L, or whose domains exceed 64 sites a side, are left out)."""
+    out = [("reference", L, L, L * L)] if L <= 64 else []
+    parts = [(f"stripes N_D={n}", L // n, L, n) for n in (2, 4)]
+    parts += [(f"checkerboard N_D={n * n}", L // n, L // n, n) for n in (2, 4)]
+    for label, Bx, By, n in parts:
+        if L % n or Bx < 1 or Bx > 64 or By > 64:
             continue
         for NI in (1, 2, 5, 10):
-            out.append((f"checkerboard N_D={nd_side * nd_side} N_I={NI}", B, NI))
+            out.append((f"{label} N_I={NI}", Bx, By, NI))
     return out
 
 
@@ -39,16 +43,16 @@ def run_study(kmc, L=12, n_traj=500, total_steps=160000, sample_steps=None, T=2.
     sample_steps = sample_steps or L * L
     ic = analysis.circle_initial_condition(L)
     results = []
-    for label, B, NI in (settings or settings_2d(L)):
-        nd = (L // B) ** 2
+    for label, B, By, NI in (settings or settings_2d(L)):
+        nd = (L // B) * (L // By)
         per_sweep = NI * nd
         every = max(1, int(round(sample_steps / per_sweep)))
         n_sweeps = max(every, (total_steps // (per_sweep * every)) * every)
         t0 = time.perf_counter()
         rec = analysis.run_setting(kmc, L, B, NI, T, n_traj, n_sweeps, every, seed + len(results),
-                                   init_spins=ic)
+                                   init_spins=ic, tile_rows=By)
         sec = time.perf_counter() - t0
-        results.append(dict(label=label, tile=B, NI=NI, ND=nd, rec=rec, sec=sec,
+        results.append(dict(label=label, tile=B, tile_rows=By, NI=NI, ND=nd, rec=rec, sec=sec,
                             ticks=n_traj * n_sweeps * per_sweep))
         if verbose:
             print(f"[study] {label}: {n_sweeps} sweeps, {rec.shape[1]} samples, {sec:.2f} s",
@@ -74,7 +78,8 @@ def analyse(results, L, eq_fraction=0.5, max_lag_samples=400):
         s = r["rec"]["steps"][0].astype(float)
         H = analysis.observable(r["rec"], L, kind="H")
         chi2 = analysis.response_error(s_ref, H_ref, s, H, taus[0], tau)
-        out.append(dict(setting=r["label"], tile=r["tile"], N_D=r["ND"], N_I=r["NI"],
+        out.append(dict(setting=r["label"], tile=r["tile"], tile_rows=r["tile_rows"],
+                        N_D=r["ND"], N_I=r["NI"],
                         tau_steps=tau, eta=analysis.efficiency(taus[0], tau), chi2=chi2,
                         e_final=float(H[:, -1].mean()), gpu_seconds=r["sec"],
                         site_updates_per_s=r["ticks"] / r["sec"]))
@@ -92,6 +97,7 @@ def save_study(path, results, L):
         arrays[f"s{k}_B"] = rec["B"].astype(np.int32)
     arrays["labels"] = np.array([r["label"] for r in results])
     arrays["tile"] = np.array([r["tile"] for r in results])
+    arrays["tile_rows"] = np.array([r["tile_rows"] for r in results])
     arrays["NI"] = np.array([r["NI"] for r in results])
     arrays["L"] = np.array(L)
     np.savez_compressed(path, **arrays)
@@ -111,8 +117,9 @@ def load_study(path):
         rec["M"] = M
         rec["B"] = z[f"s{k}_B"]
         B = int(z["tile"][k])
-        out.append(dict(label=str(label), tile=B, NI=int(z["NI"][k]), ND=(L // B) ** 2, rec=rec,
-                        sec=float("nan"), ticks=0))
+        By = int(z["tile_rows"][k]) if "tile_rows" in z else B
+        out.append(dict(label=str(label), tile=B, tile_rows=By, NI=int(z["NI"][k]),
+                        ND=(L // B) * (L // By), rec=rec, sec=float("nan"), ticks=0))
     return out, L
 
 

@@ -99,17 +99,36 @@ def test_study_save_and_load_round_trip(tmp_path):
     from paper_1403_4674_amd import experiments
     rng = np.random.default_rng(3)
     res = []
-    for label, B, NI in [("reference", 12, 144), ("checkerboard N_D=4 N_I=2", 6, 2)]:
+    for label, B, By, NI in [("reference", 12, 12, 144), ("stripes N_D=4 N_I=2", 3, 12, 2)]:
         rec = np.zeros((5, 7), [("steps", "<i8"), ("M", "<i8"), ("B", "<i8"), ("t", "<f8")])
         rec["steps"] = np.arange(7)[None, :] * 144
         rec["M"] = rng.integers(-144, 145, (5, 7))
         rec["B"] = rng.integers(-288, 289, (5, 7))
-        res.append(dict(label=label, tile=B, NI=NI, ND=(12 // B) ** 2, rec=rec, sec=1.0, ticks=1))
+        res.append(dict(label=label, tile=B, tile_rows=By, NI=NI, ND=(12 // B) * (12 // By),
+                        rec=rec, sec=1.0, ticks=1))
     p = tmp_path / "study.npz"
     experiments.save_study(str(p), res, 12)
     back, L = experiments.load_study(str(p))
     assert L == 12 and [r["label"] for r in back] == [r["label"] for r in res]
     for a, b in zip(res, back):
-        assert (a["tile"], a["NI"], a["ND"]) == (b["tile"], b["NI"], b["ND"])
+        assert (a["tile"], a["tile_rows"], a["NI"], a["ND"]) == \
+            (b["tile"], b["tile_rows"], b["NI"], b["ND"])
         for f in ("steps", "M", "B"):
             assert np.array_equal(a["rec"][f], b["rec"][f])
+
+
+def test_study_settings_cover_the_papers_partitions():
+    from paper_1403_4674_amd import experiments
+    st = experiments.settings_2d(12)
+    labels = [x[0] for x in st]
+    assert labels[0] == "reference" and st[0][1:] == (12, 12, 144)
+    for n in (2, 4):
+        for NI in (1, 2, 5, 10):
+            assert (f"stripes N_D={n} N_I={NI}", 12 // n, 12, NI) in st
+    for n in (4, 16):
+        for NI in (1, 2, 5, 10):
+            side = 12 // int(n ** 0.5)
+            assert (f"checkerboard N_D={n} N_I={NI}", side, side, NI) in st
+    big = experiments.settings_2d(100)   # no 100-site-high domains
+    assert all(By <= 64 and Bx <= 64 for _, Bx, By, _ in big)
+    assert {x[0].split(" N_I")[0] for x in big} == {"checkerboard N_D=4", "checkerboard N_D=16"}

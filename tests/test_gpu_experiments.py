@@ -1,6 +1,6 @@
 """The 2D parallelisation study on the GPU (needs an MI355X): the batched
 trajectories of every setting (unpartitioned reference as one periodic
-domain, checkerboards of 6x6 and 3x3 domains) are the oracle's, bit for bit,
+domain, a checkerboard of 6x6 domains, four 12x3 stripes) are the oracle's, bit for bit,
 and the analysis runs on them."""
 import numpy as np
 import pytest
@@ -20,18 +20,18 @@ def torch_cuda():
 
 def test_small_study_trajectories_match_oracle(torch_cuda, oracle_lib):
     L, n_traj = 12, 24
-    settings = [("reference", 12, 144), ("cb4 NI=2", 6, 2), ("cb16 NI=5", 3, 5)]
+    settings = [("reference", 12, 12, 144), ("cb4 NI=2", 6, 6, 2), ("stripes4 NI=5", 3, 12, 5)]
     say("12x12 study, 24 trajectories per setting")
     res = experiments.run_study(kmc, L, n_traj, total_steps=6000, settings=settings,
                                 verbose=False)
     ic = analysis.circle_initial_condition(L)
-    for r, (label, B, NI) in zip(res, settings):
+    for r, (label, B, By, NI) in zip(res, settings):
         rec = r["rec"]
         assert rec.shape[0] == n_traj and rec["steps"][0, 0] == 0
         seed = 2024 + res.index(r)
         for rho in (0, n_traj - 1):
-            d = dict(L=L, tile=B, T=2.4, steps_per_visit=NI, rate_model=kmc.RATE_BARKER,
-                     init=kmc.INIT_GIVEN)
+            d = dict(L=L, tile=B, tile_rows=By, T=2.4, steps_per_visit=NI,
+                     rate_model=kmc.RATE_BARKER, init=kmc.INIT_GIVEN)
             o = oracle_for(oracle_lib, d, seed, rho, ic)
             every = int(round(rec["sweep"][rho, 2] - rec["sweep"][rho, 1]))
             n_sweeps = int(rec["sweep"][rho, -1])
