@@ -86,20 +86,32 @@ enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
 #define KMC_F_TIMING 0x80u     /* record HIP events around every launch of the
                                   hot kernel (the phase kernel, or the
                                   persistent kernels), read by kmc_get_timing */
+#define KMC_F_RESIDENT 0x200u  /* resident form: one workgroup per replica keeps
+                                  the whole lattice, its class codes and
+                                  per-row class counts in LDS for every sweep
+                                  of the call (one launch; no staging per
+                                  visit).  Needs 3 <= L <= 128 and at most 16
+                                  domains along x for every replica; the only
+                                  form for domains wider or taller than 64
+                                  sites (the others return
+                                  KMC_EUNSUPPORTED for them).  Not with
+                                  KMC_F_PERSISTENT, KMC_F_FLOW or KMC_F_GRAPH
+                                  (KMC_EINVAL)                                */
 /* flags of kmc_backward_score and kmc_observables */
 #define KMC_F_DEVICE_OUT 0x10u /* output pointer is device memory; the copy is
                                   enqueued on the context stream, no sync     */
 
 /* One replica.  Domains are `tile` = Bx sites wide and `tile_rows` = By high
  * (0: By = Bx), the paper's fixed equal partition (Sec. 2.2, Fig. 1):
- * 1 <= Bx, By <= 64, L % Bx == 0, L % By == 0.  Square domains with L/B even
+ * 1 <= Bx, By <= 128, L % Bx == 0, L % By == 0.  Square domains with L/B even
  * give the 4-colour checkerboard, By = L gives vertical stripes, Bx = By = L
  * the unpartitioned lattice as one periodic domain (N_D = 1, the paper's
  * reference dynamics); odd domain counts are allowed too.  The domain grid is
  * coloured per axis (1 colour for one domain, 2 for an even count, 3 for an
  * odd count) and the schedule runs its colours in a uniformly drawn order
  * (Eq. (schedule)) or as a palindrome.  An axis with a single domain wraps
- * inside the domain and needs a side >= 3.  steps_per_visit = N_I ticks per
+ * inside the domain and needs a side >= 3.  Domains of 65 to 128 sites a
+ * side (L <= 128) run in the resident form only (KMC_F_RESIDENT).  steps_per_visit = N_I ticks per
  * domain process (Sec. 2.2); 0 selects Bx*By (one Monte Carlo step per site
  * per visit). */
 typedef struct {

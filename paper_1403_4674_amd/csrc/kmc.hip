@@ -17,6 +17,7 @@
 #include "kmc.h"
 #include "kmc_device.h"
 #include "kmc_multi.h"
+#include "kmc_resident.h"
 
 using kmcdev::Ctl;
 using kmcdev::MItem;
@@ -250,6 +251,14 @@ bool multi_ok(const Rep &rp) {
 // taller than 32.
 bool wide(const Rep &rp) { return rp.B > 32 || rp.By > 32; }
 
+// Domains over 64 sites a side: only the resident form holds them.
+bool big(const Rep &rp) { return rp.B > 64 || rp.By > 64; }
+
+// Replicas the resident form can hold in one workgroup's LDS.
+bool resident_ok(const Rep &rp) {
+    return rp.L >= 3 && rp.L <= kmcdev::kResMaxL && rp.NT <= kmcdev::kResMaxNTx;
+}
+
 void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     auto bad = [&](const char *why) {
         fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": " + why);
@@ -257,8 +266,10 @@ void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
         bad("J, h must be finite and T > 0");
     const int by = tile_rows_of(d);
-    if (d.tile < 1 || d.tile > 64) bad("tile must be in [1, 64]");
-    if (by < 1 || by > 64) bad("tile_rows must be 0 or in [1, 64]");
+    if (d.tile < 1 || d.tile > 128) bad("tile must be in [1, 128]");
+    if (by < 1 || by > 128) bad("tile_rows must be 0 or in [1, 128]");
+    if ((d.tile > 64 || by > 64) && d.L > kmcdev::kResMaxL)
+        bad("domains over 64 sites a side need L <= 128 (resident form)");
     if (d.L < d.tile || d.L % d.tile) bad("L must be a multiple of tile");
     if (d.L < by || d.L % by) bad("L must be a multiple of tile_rows");
     if (d.L == d.tile && d.tile < 3)
@@ -431,6 +442,23 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t n_sweeps, uint32_t flags) 
     }
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "persistent launch");
+}
+
+// Resident form: one workgroup per replica, as many wavefronts as the
+// largest colour class has domains (at most 16).
+template <bool SCORE>
+void launch_resident(kmc_ctx *c, KParams K, int64_t n_sweeps) {
+    int waves = 1, lds = 0;
+    for (const Rep &rp : c->reps) {
+        waves = std::max(waves, std::min(max_per_colour(rp), kmcdev::kResMaxWaves));
+        lds = std::max(lds, kmcdev::resident_lds_bytes(rp.L, rp.NT));
+    }
+    timed_launch(c, [&] {
+        hipLaunchKernelGGL((kmcdev::k_resident<SCORE>), dim3(c->n_rep), dim3(64 * waves),
+                           (unsigned)lds, c->stream, K, n_sweeps);
+    });
+    hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
+    launch_check(c, "resident launch");
 }
 
 void ensure_records(kmc_ctx *c, int64_t need) {
@@ -826,6 +854,24 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             fail(c, KMC_EINVAL, "KMC_F_TIMING is not available with KMC_F_GRAPH");
         if ((flags & KMC_F_FLOW) && (flags & KMC_F_PERSISTENT))
             fail(c, KMC_EINVAL, "KMC_F_FLOW applies to the phase-by-phase form only");
+        if (flags & KMC_F_RESIDENT) {
+            if (flags & (KMC_F_PERSISTENT | KMC_F_FLOW | KMC_F_GRAPH))
+                fail(c, KMC_EINVAL,
+                     "KMC_F_RESIDENT is not available with KMC_F_PERSISTENT, KMC_F_FLOW or "
+                     "KMC_F_GRAPH");
+            for (int rho = 0; rho < c->n_rep; ++rho)
+                if (!resident_ok(c->reps[rho]))
+                    fail(c, KMC_EINVAL,
+                         "replica " + std::to_string(rho) +
+                             ": the resident form needs 3 <= L <= 128 and at most 16 domains "
+                             "along x");
+        } else {
+            for (int rho = 0; rho < c->n_rep; ++rho)
+                if (big(c->reps[rho]))
+                    fail(c, KMC_EUNSUPPORTED,
+                         "replica " + std::to_string(rho) +
+                             ": domains over 64 sites a side run only with KMC_F_RESIDENT");
+        }
         if (n_sweeps == 0) return KMC_OK;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
@@ -866,7 +912,12 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         }
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, c->stream, c->d_ctl,
                            (int64_t)0, c->n_rec, (int64_t)record_every, c->sweep);
-        if (flags & KMC_F_PERSISTENT) {
+        if (flags & KMC_F_RESIDENT) {
+            if (score)
+                launch_resident<true>(c, K, n_sweeps);
+            else
+                launch_resident<false>(c, K, n_sweeps);
+        } else if (flags & KMC_F_PERSISTENT) {
             if (score)
                 launch_persistent<true>(c, K, n_sweeps, flags);
             else if (flags & KMC_F_GRAPH)
@@ -979,7 +1030,9 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         K.write_records = 0;
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
-        if (c->ck_flags & KMC_F_PERSISTENT) {
+        if (c->ck_flags & KMC_F_RESIDENT) {
+            launch_resident<true>(c, K, c->ck_n_sweeps);
+        } else if (c->ck_flags & KMC_F_PERSISTENT) {
             launch_persistent<true>(c, K, c->ck_n_sweeps, c->ck_flags);
         } else {
             c->flow = (c->ck_flags & KMC_F_FLOW) != 0;

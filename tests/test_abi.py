@@ -64,7 +64,8 @@ BAD = [
     dict(L=2, tile=2, T=2.0),     # one domain with fewer than three rows
     dict(L=12, tile=4, tile_rows=5, T=2.0),    # L not a multiple of tile_rows
     dict(L=16, tile=8, tile_rows=-1, T=2.0),   # tile_rows below 0
-    dict(L=128, tile=16, tile_rows=128, T=2.0),  # tile_rows above 64
+    dict(L=256, tile=16, tile_rows=256, T=2.0),  # tile_rows above 128
+    dict(L=192, tile=96, T=2.0),  # domains over 64 sites a side with L > 128
     dict(L=2, tile=1, tile_rows=2, T=2.0),     # wrapped column with two sites
     dict(L=2, tile=2, tile_rows=1, T=2.0),     # wrapped row with two sites
     dict(L=8, tile=0, T=2.0),     # tile below 1
