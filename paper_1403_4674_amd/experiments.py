@@ -6,10 +6,14 @@ with checkerboards (N_D = 4, 16) for N_I in {1, 2, 5, 10}; each setting is a
 batch of independent trajectories in one persistent launch.  The analysis
 (tau, eta, chi^2) is `analysis.py`.
 
-    python -m paper_1403_4674_amd.experiments --L 12 --traj 500
+    python -m paper_1403_4674_amd.experiments --L 12     # 500 x 1.6e5 steps
+    python -m paper_1403_4674_amd.experiments --L 100    # 50 x 1.6e7 steps
 
-prints one JSON line per setting and a summary line; `--save FILE.npz`
-also keeps every setting's trajectories (steps, M, B) for re-analysis.
+(Table 1's trajectory counts and run lengths) prints one JSON line per
+setting and a summary line; `--save FILE.npz` also keeps every setting's
+trajectories (steps, M, B) for re-analysis.  Lattices up to 128 run in the
+resident form (the whole lattice in one workgroup's LDS), which holds the
+unpartitioned 100 x 100 reference and the 100-high stripes.
 """
 import json
 import time
@@ -19,16 +23,27 @@ import numpy as np
 from . import analysis
 
 
+# Table 1: trajectories and steps per trajectory of the 2D runs
+PAPER_RUNS = {12: (500, 160_000), 100: (50, 16_000_000)}
+
+
+def max_side(L):
+    """Largest domain side the GPU runs for lattice side L (the resident form
+    holds domains up to the lattice itself for L <= 128)."""
+    return L if L <= 128 else 64
+
+
 def settings_2d(L):
     """(label, domain width, domain height, N_I) of the unpartitioned
     reference, vertical stripes with N_D = 2 and 4, and checkerboards with
     N_D = 4 and 16, each for N_I in {1, 2, 5, 10} (partitions that do not
-    divide L, or whose domains exceed 64 sites a side, are left out)."""
-    out = [("reference", L, L, L * L)] if L <= 64 else []
+    divide L, or whose domains are too large for the GPU, are left out)."""
+    top = max_side(L)
+    out = [("reference", L, L, L * L)] if L <= top else []
     parts = [(f"stripes N_D={n}", L // n, L, n) for n in (2, 4)]
     parts += [(f"checkerboard N_D={n * n}", L // n, L // n, n) for n in (2, 4)]
     for label, Bx, By, n in parts:
-        if L % n or Bx < 1 or Bx > 64 or By > 64:
+        if L % n or Bx < 1 or Bx > top or By > top:
             continue
         for NI in (1, 2, 5, 10):
             out.append((f"{label} N_I={NI}", Bx, By, NI))
@@ -49,8 +64,9 @@ def run_study(kmc, L=12, n_traj=500, total_steps=160000, sample_steps=None, T=2.
         every = max(1, int(round(sample_steps / per_sweep)))
         n_sweeps = max(every, (total_steps // (per_sweep * every)) * every)
         t0 = time.perf_counter()
+        flags = kmc.F_RESIDENT if L <= 128 else kmc.F_PERSISTENT
         rec = analysis.run_setting(kmc, L, B, NI, T, n_traj, n_sweeps, every, seed + len(results),
-                                   init_spins=ic, tile_rows=By)
+                                   init_spins=ic, tile_rows=By, flags=flags)
         sec = time.perf_counter() - t0
         results.append(dict(label=label, tile=B, tile_rows=By, NI=NI, ND=nd, rec=rec, sec=sec,
                             ticks=n_traj * n_sweeps * per_sweep))
@@ -60,27 +76,43 @@ def run_study(kmc, L=12, n_traj=500, total_steps=160000, sample_steps=None, T=2.
     return results
 
 
-def analyse(results, L, eq_fraction=0.5, max_lag_samples=400):
+def analyse(results, L, eq_fraction=0.5, max_lag_samples=400, n_boot=30, boot_seed=0):
     """tau of A = H m from the equilibrium halves, eta and chi^2 (A = H) of
-    every setting against the reference (the first result)."""
+    every setting against the reference (the first result).  Also: chi^2
+    without the time rescaling (tau_PAR = tau_REF), and bootstrap standard
+    errors of tau and eta (trajectories resampled n_boot times; eta's error
+    combines the two taus' in quadrature)."""
     ref = results[0]
-    out = []
-    taus = []
-    for r in results:
+    rng = np.random.default_rng(boot_seed)
+
+    def tau_of(r, rows=None):
         s = r["rec"]["steps"][0].astype(float)
         Am = analysis.observable(r["rec"], L, kind="Hm")
+        if rows is not None:
+            Am = Am[rows]
         k0 = int(len(s) * eq_fraction)
         C = analysis.autocorrelation(Am[:, k0:], max_lag_samples)
-        taus.append(analysis.fit_tau(C, s[1] - s[0]))
+        return analysis.fit_tau(C, s[1] - s[0])
+
+    taus, ses = [], []
+    for r in results:
+        taus.append(tau_of(r))
+        n = r["rec"].shape[0]
+        boot = [tau_of(r, rng.integers(0, n, n)) for _ in range(n_boot)]
+        ses.append(float(np.std(boot)) if n_boot > 1 else float("nan"))
     s_ref = ref["rec"]["steps"][0].astype(float)
     H_ref = analysis.observable(ref["rec"], L, kind="H")
-    for r, tau in zip(results, taus):
+    out = []
+    for r, tau, se in zip(results, taus, ses):
         s = r["rec"]["steps"][0].astype(float)
         H = analysis.observable(r["rec"], L, kind="H")
         chi2 = analysis.response_error(s_ref, H_ref, s, H, taus[0], tau)
+        chi2_raw = analysis.response_error(s_ref, H_ref, s, H, taus[0], taus[0])
+        eta = analysis.efficiency(taus[0], tau)
+        eta_se = eta * float(np.hypot(ses[0] / taus[0], se / tau)) if r is not ref else 0.0
         out.append(dict(setting=r["label"], tile=r["tile"], tile_rows=r["tile_rows"],
-                        N_D=r["ND"], N_I=r["NI"],
-                        tau_steps=tau, eta=analysis.efficiency(taus[0], tau), chi2=chi2,
+                        N_D=r["ND"], N_I=r["NI"], tau_steps=tau, tau_se=se,
+                        eta=eta, eta_se=eta_se, chi2=chi2, chi2_unscaled=chi2_raw,
                         e_final=float(H[:, -1].mean()), gpu_seconds=r["sec"],
                         site_updates_per_s=r["ticks"] / r["sec"]))
     return out
@@ -131,14 +163,24 @@ def main():
     from . import kmc
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, default=12)
-    ap.add_argument("--traj", type=int, default=500)
-    ap.add_argument("--steps", type=int, default=160000)
+    ap.add_argument("--traj", type=int, default=0, help="default: Table 1's count")
+    ap.add_argument("--steps", type=int, default=0, help="default: Table 1's length")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--save", default="", help="write the trajectories to this .npz")
+    ap.add_argument("--only", default="",
+                    help="comma-separated labels to keep besides the reference, e.g. "
+                         "'stripes N_D=2 N_I=1,stripes N_D=2 N_I=2'")
     args = ap.parse_args()
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
-    res = run_study(kmc, args.L, args.traj, args.steps, seed=args.seed)
+    traj, steps = PAPER_RUNS.get(args.L, (100, 100 * args.L * args.L))
+    args.traj = args.traj or traj
+    args.steps = args.steps or steps
+    settings = settings_2d(args.L)
+    if args.only:
+        keep = {x.strip() for x in args.only.split(",")}
+        settings = [st for st in settings if st[0] == "reference" or st[0] in keep]
+    res = run_study(kmc, args.L, args.traj, args.steps, seed=args.seed, settings=settings)
     rows = analyse(res, args.L)
     if args.save:
         save_study(args.save, res, args.L)

@@ -129,6 +129,9 @@ def test_study_settings_cover_the_papers_partitions():
         for NI in (1, 2, 5, 10):
             side = 12 // int(n ** 0.5)
             assert (f"checkerboard N_D={n} N_I={NI}", side, side, NI) in st
-    big = experiments.settings_2d(100)   # no 100-site-high domains
-    assert all(By <= 64 and Bx <= 64 for _, Bx, By, _ in big)
-    assert {x[0].split(" N_I")[0] for x in big} == {"checkerboard N_D=4", "checkerboard N_D=16"}
+    big = experiments.settings_2d(100)   # resident form: the full reference
+    assert big[0] == ("reference", 100, 100, 10000)
+    assert {x[0].split(" N_I")[0] for x in big[1:]} == {
+        "stripes N_D=2", "stripes N_D=4", "checkerboard N_D=4", "checkerboard N_D=16"}
+    huge = experiments.settings_2d(256)  # beyond the resident form: domains <= 64
+    assert all(By <= 64 and Bx <= 64 for _, Bx, By, _ in huge)
