@@ -42,10 +42,10 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
-    "kernel_source_sha256": "a6537e98c88f3faa81869d71d945dede29c7e371ec79aa1e662e7c3604f7340b",
-    "fetch_scale": 1048576.0 / 524308.19, "write_scale": 1048576.0 / 1048576.0,
-    "kib": {"k_flow<uint32_t,false>": (3491.48, 1184.13),
-            "k_phase<uint32_t,false>": (914.01, 288.0)},
+    "kernel_source_sha256": "cedd12a1a0b859a16739fb764a1e5dcbce6f93788478302d3700c712919f7ebd",
+    "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
+    "kib": {"k_flow<uint32_t,false,false>": (3508.81, 1184.12),
+            "k_phase<uint32_t,false,false>": (932.01, 288.0)},
 }
 # algorithmic bytes per colour phase of the plain workload: each of the 256
 # domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the
@@ -53,7 +53,7 @@ PLAIN_TRAFFIC = {
 PLAIN_ALG_BYTES_PER_PHASE = 256 * (2 * 32 * 32 + 4 * 32)
 
 
-def plain_traffic(kernel):
+def plain_traffic(kernel, sweeps_per_launch=1.0):
     import hashlib
     t = PLAIN_TRAFFIC
     if kernel not in t["kib"]:
@@ -63,7 +63,9 @@ def plain_traffic(kernel):
         if hashlib.sha256(f.read()).hexdigest() != t["kernel_source_sha256"]:
             return None
     fetch, write = t["kib"][kernel]
-    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+    per = (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+    # dataflow launches: the counters are kept per sweep
+    return per * (sweeps_per_launch if kernel.startswith("k_flow") else 1.0)
 
 
 def timed(fn, stream):
@@ -105,7 +107,7 @@ def plain(args, kmc, workloads, phased=False, steps=None):
     return dict(sec=sec, ticks=ticks, events=events, launches=launches,
                 kernel_sec=None if kernel_ms is None else kernel_ms / 1e3,
                 desc=d, seed=seed, phased=phased,
-                kernel="k_phase<uint32_t,false>" if phased else "k_flow<uint32_t,false>")
+                kernel="k_phase<uint32_t,false,false>" if phased else "k_flow<uint32_t,false,false>")
 
 
 def parse_tiles(text):
@@ -260,6 +262,7 @@ def main():
     # each launch; with --graph, the timed region over the launch count
     kernel_sec = p["kernel_sec"] if p["kernel_sec"] is not None else p["sec"]
     per_launch = kernel_sec / p["launches"]
+    sweeps_per_launch = 0.25 if p["phased"] else args.steps / p["launches"]
     d = p["desc"]
     ops = OPS_PER_TICK * p["ticks"] + OPS_PER_EVENT * p["events"]
     achieved = ops / kernel_sec
@@ -280,7 +283,8 @@ def main():
         "config": {"workload": "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain",
                    "L": d["L"], "tile": d["tile"], "steps_per_visit": d["steps_per_visit"],
                    "T": d["T"], "seed": p["seed"], "graph": bool(args.graph),
-                   "form": "phase_launches" if p["phased"] else "one_dataflow_launch_per_sweep"},
+                   "form": "phase_launches" if p["phased"]
+                   else "dataflow_launches_of_up_to_64_sweeps"},
         "events_per_s": p["events"] / p["sec"],
         "roofline": {
             "bound": "alu",
@@ -289,9 +293,10 @@ def main():
             "peak": ALU_PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / ALU_PEAK_LANE_OPS,
-            "traffic": plain_traffic(p["kernel"]),
+            "traffic": plain_traffic(p["kernel"], sweeps_per_launch),
             "traffic_unit": "B/launch",
-            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES_PER_PHASE * (1 if p["phased"] else 4),
+            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES_PER_PHASE * 4 * sweeps_per_launch,
+            "sweeps_per_launch": sweeps_per_launch,
             "per_launch_ms": per_launch * 1e3,
             "launches": p["launches"],
             "ops_per_launch": ops / p["launches"],

@@ -83,7 +83,10 @@ struct kmc_ctx {
     RepAcc *d_acc = nullptr;
     Record *d_rec = nullptr;
     Ctl *d_ctl = nullptr;
-    int64_t *d_done = nullptr;  // per-domain visit counters of the one-launch sweep
+    int64_t *d_done = nullptr;  // per-domain visit counters of the one-launch sweeps
+    // per-sweep slots of a dataflow launch (allocated on first use)
+    int64_t *d_flow_acc = nullptr;  // [kFlowMaxSweeps][n_rep][3]
+    double *d_flow_clk = nullptr;   // [kFlowMaxSweeps][n_dom][2]
     bool graph_flow = false;    // the cached phase graph was captured with flow
     bool flow = false;          // phase-by-phase sweeps as one dataflow launch
     int32_t *d_task_rep = nullptr;
@@ -306,6 +309,9 @@ KParams params(kmc_ctx *c) {
     K.seed = c->seed;
     K.write_records = 1;
     K.task_begin = 0;
+    K.flow_acc = c->d_flow_acc;
+    K.flow_clk = c->d_flow_clk;
+    K.n_dom_total = c->n_dom;
     return K;
 }
 
@@ -345,33 +351,55 @@ void with_wrap(const kmc_ctx *c, int g, F f) {
 }
 
 template <bool SCORE>
+void launch_sweep(kmc_ctx *c, KParams K);
+
+// G sweeps (G <= kFlowMaxSweeps) as one dataflow launch per row-mask width
+// (replicas of the two widths never interact), then the records.
+template <bool SCORE>
+void launch_flow(kmc_ctx *c, KParams K, int G) {
+    const int64_t slots = (int64_t)G * c->n_rep * 3;
+    hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0,
+                       c->stream, c->d_flow_acc, slots, (int64_t)0);
+    timed_launch(c, [&] {
+        if (c->n_tasks32) {
+            K.task_begin = 0;
+            with_wrap(c, 0, [&](auto W) {
+                hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value>),
+                                   dim3(G * c->n_phase * c->n_tasks32), dim3(64), 0,
+                                   c->stream, K, c->n_tasks32, c->n_phase, c->d_done);
+            });
+        }
+        if (c->n_tasks > c->n_tasks32) {
+            const int nt = c->n_tasks - c->n_tasks32;
+            K.task_begin = c->n_tasks32;
+            with_wrap(c, 1, [&](auto W) {
+                hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value>),
+                                   dim3(G * c->n_phase * nt), dim3(64), 0, c->stream, K, nt,
+                                   c->n_phase, c->d_done);
+            });
+        }
+    });
+    hipLaunchKernelGGL(kmcdev::k_flow_close, dim3(c->n_rep), dim3(64), 0, c->stream, K, G);
+    hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, (int64_t)G);
+    launch_check(c, "flow launch");
+}
+
+// n sweeps of the phase-by-phase form (dataflow launches of up to
+// kFlowMaxSweeps sweeps when c->flow).
+template <bool SCORE>
+void run_sweeps(kmc_ctx *c, KParams K, int64_t n) {
+    if (c->flow) {
+        for (int64_t i = 0; i < n; i += kmcdev::kFlowMaxSweeps)
+            launch_flow<SCORE>(c, K, (int)std::min<int64_t>(kmcdev::kFlowMaxSweeps, n - i));
+        return;
+    }
+    for (int64_t i = 0; i < n; ++i) launch_sweep<SCORE>(c, K);
+}
+
+template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K) {
     if (c->flow) {
-        // the whole sweep in one launch per row-mask width (replicas of the
-        // two widths never interact)
-        timed_launch(c, [&] {
-            if (c->n_tasks32) {
-                K.task_begin = 0;
-                with_wrap(c, 0, [&](auto W) {
-                    hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value>),
-                                       dim3(c->n_phase * c->n_tasks32), dim3(64), 0, c->stream,
-                                       K, c->n_tasks32, c->d_done);
-                });
-            }
-            if (c->n_tasks > c->n_tasks32) {
-                const int nt = c->n_tasks - c->n_tasks32;
-                K.task_begin = c->n_tasks32;
-                with_wrap(c, 1, [&](auto W) {
-                    hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value>),
-                                       dim3(c->n_phase * nt), dim3(64), 0, c->stream, K, nt,
-                                       c->d_done);
-                });
-            }
-        });
-        hipLaunchKernelGGL(kmcdev::k_sweep_end, dim3(c->n_rep), dim3(64), 0, c->stream, K);
-        hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl,
-                           (int64_t)1);
-        launch_check(c, "sweep launch");
+        launch_flow<SCORE>(c, K, 1);
         return;
     }
     for (int p = 0; p < c->n_phase; ++p) {
@@ -459,6 +487,14 @@ void launch_resident(kmc_ctx *c, KParams K, int64_t n_sweeps) {
     });
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, n_sweeps);
     launch_check(c, "resident launch");
+}
+
+// Per-sweep slots of the dataflow launches, allocated once (captured graphs
+// keep their addresses).
+void ensure_flow_slots(kmc_ctx *c) {
+    if (c->d_flow_acc) return;
+    c->d_flow_acc = alloc_n<int64_t>(c, (int64_t)kmcdev::kFlowMaxSweeps * c->n_rep * 3);
+    c->d_flow_clk = alloc_n<double>(c, (int64_t)kmcdev::kFlowMaxSweeps * std::max(c->n_dom, 1) * 2);
 }
 
 void ensure_records(kmc_ctx *c, int64_t need) {
@@ -579,7 +615,7 @@ void destroy_buffers(kmc_ctx *c) {
                     c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
                     c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
                     c->r_ctl,   c->d_bins,  c->d_tmp_rec, c->d_order_nm, c->d_items,
-                    c->d_done};
+                    c->d_done, c->d_flow_acc, c->d_flow_clk};
     for (void *p : bufs) dev_free(c, p);
 }
 
@@ -894,10 +930,13 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         }
         c->timing = (flags & KMC_F_TIMING) != 0;
         c->flow = (flags & KMC_F_FLOW) != 0;
-        if (c->flow)  // counters restart with every run (a replay may go back in sweeps)
+        if (c->flow) {
+            ensure_flow_slots(c);
+            // counters restart with every run (a replay may go back in sweeps)
             hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((c->n_dom + 255) / 256)),
                                dim3(256), 0, c->stream, c->d_done, (int64_t)c->n_dom,
                                (int64_t)0);
+        }
         KParams K = params(c);
         const bool score = (flags & KMC_F_SCORE) != 0;
         if (score || (flags & KMC_F_CHECKPOINT)) c->fused_score = false;
@@ -927,12 +966,10 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         } else if (flags & KMC_F_GRAPH) {
             run_graph(c, n_sweeps);
         } else {
-            for (int64_t i = 0; i < n_sweeps; ++i) {
-                if (score)
-                    launch_sweep<true>(c, K);
-                else
-                    launch_sweep<false>(c, K);
-            }
+            if (score)
+                run_sweeps<true>(c, K, n_sweeps);
+            else
+                run_sweeps<false>(c, K, n_sweeps);
         }
         if (score) {
             c->fused_score = true;
@@ -1039,7 +1076,10 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
             if (c->flow)
                 hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((c->n_dom + 255) / 256)),
                                    dim3(256), 0, s, c->d_done, (int64_t)c->n_dom, (int64_t)0);
-            for (int64_t i = 0; i < c->ck_n_sweeps; ++i) launch_sweep<true>(c, K);
+            if (c->flow) ensure_flow_slots(c);
+            K.flow_acc = c->d_flow_acc;
+            K.flow_clk = c->d_flow_clk;
+            run_sweeps<true>(c, K, c->ck_n_sweeps);
         }
         hip_check(c, hipMemcpy2DAsync(score, (size_t)capacity * 2 * sizeof(double), c->d_bins,
                                       (size_t)n_bins * 2 * sizeof(double),

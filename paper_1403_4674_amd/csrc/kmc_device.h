@@ -112,6 +112,11 @@ struct KParams {
     uint64_t seed;
     int32_t write_records;
     int32_t task_begin;       // first phase task of this launch
+    // one-launch sweeps: per-sweep changes of M, B, events [sweep][replica][3]
+    // and each domain's clock after the sweep [sweep][domain] (sum, comp)
+    int64_t *flow_acc;
+    double *flow_clk;
+    int32_t n_dom_total;      // domain records of all replicas
 };
 
 // ------------------------------------------------------------------ Philox
@@ -990,28 +995,42 @@ __device__ inline int visits_before(const Rep &rp, uint64_t pos_of, int col, int
 }
 
 constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;
+constexpr int kFlowMaxSweeps = 64;  // sweeps of one dataflow launch
 
-// One whole sweep of the phase-by-phase form in one launch.  Block b runs
-// phase p = b / n_tasks of task b % n_tasks, once every visit of a
-// neighbouring domain (and, in the palindrome, of the domain itself) that
-// precedes it in the sweep's sequential order has finished.  Each domain
-// publishes 4 w + (its visits so far in sweep w) with a device-scope
-// release after writing its tile back; waiters read it with a device-scope
-// acquire.  The halo every visit reads is therefore exactly the one of the
-// sequential order, so the results equal the phase-by-phase launches bit
-// for bit, while domains of non-adjacent colours, and domains whose
-// neighbours finished early, run ahead instead of waiting for a whole
-// phase.  Blocks are numbered phase-major, so a block only waits on blocks
-// numbered before it.  A wait that exceeds kFlowMaxPolls polls sets ctl->err
-// and gives up (the host reports the run as failed), so no wave can hang.
+// G whole sweeps of the phase-by-phase form in one launch.  Block b runs
+// sweep g = b / (P n_tasks), phase p = (b / n_tasks) mod P, task
+// b mod n_tasks (P phases per sweep).  A visit starts once every visit that
+// precedes it in the sequential order and touches its halo or its tile has
+// finished: the visits of its four neighbouring domains earlier in this
+// sweep's schedule, the neighbours' visits of the previous sweep (all of
+// them: sweeps are sequential), and its own previous visit.  Each domain
+// publishes 4 w + (its visits so far in sweep w) with a device-scope release
+// after writing its tile back; waiters poll it with relaxed device-scope
+// loads and then take one device-scope acquire fence.  A visit that follows
+// ours waits for ours the same way, so no visit reads a
+// halo a later visit has already changed.  The halo every visit reads is
+// therefore exactly the one of the sequential order, and results equal the
+// phase-by-phase launches bit for bit, while domains of non-adjacent
+// colours, domains whose neighbours finished early, and the next sweep's
+// early visits run ahead.  Blocks are numbered sweep- and phase-major, so a
+// block only waits on blocks numbered before it.  A wait that exceeds
+// kFlowMaxPolls polls sets ctl->err and gives up (the host reports the run
+// as failed), so no wave can hang.  Sweeps overlap, so a visit adds its
+// changes of M, B and events to its sweep's slot and stores its domain's
+// clock after the sweep's last visit; k_flow_close forms the records.
 template <typename MT, bool SCORE, bool WRAP>
-__global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *done) {
+__global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase,
+                                             int64_t *done) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
-    const int p = (int)blockIdx.x / n_tasks;
-    const int task = K.task_begin + (int)blockIdx.x % n_tasks;
+    const int per_sweep = n_phase * n_tasks;
+    const int g = (int)blockIdx.x / per_sweep;
+    const int b = (int)blockIdx.x - g * per_sweep;
+    const int p = b / n_tasks;
+    const int task = K.task_begin + b % n_tasks;
     const int rho = K.task_rep[task];
     const Rep rp = K.reps[rho];
-    const uint32_t w = (uint32_t)K.ctl->sweep;
+    const int64_t run_done = K.ctl->run_done + g;  // sweeps of the run before this one
+    const uint32_t w = (uint32_t)(K.ctl->sweep + g);
     int vis;
     const int col = phase_colour(rp, K.seed, (uint32_t)rho, w, p, &vis);
     if (col < 0 || task - rp.task_off >= domains_of_colour(rp, col)) return;
@@ -1019,6 +1038,9 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
     int64_t *dn = done + rp.dom_off;
     const int64_t base = 4 * (int64_t)w;
+    // every visit of the previous sweep (counters restart with each run, and
+    // a run's first sweep follows complete sweeps)
+    const int64_t prev = run_done > 0 ? base - 4 + rp.visits : 0;
     if (__lane_id() == 0) {
         uint64_t pos_of = 0;  // 4-bit position of each colour in this sweep's order
         if (rp.sched != 1)
@@ -1027,11 +1049,13 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
         const int NT = rp.NT, NTy = rp.NTy, ty = d / NT, tx = d - ty * NT;
         auto wait_for = [&](int ey, int ex) {
             const int need = visits_before(rp, pos_of, dom_colour(rp, ey, ex), p);
-            if (need == 0) return;
+            const int64_t target = need ? base + need : prev;
+            if (target == 0) return;
             const int64_t *cnt = dn + ey * NT + ex;
             int64_t polls = 0;
-            while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                   base + need) {
+            // relaxed polls (no cache invalidation per poll); one acquire
+            // fence once every wait is over
+            while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++polls > kFlowMaxPolls) {
                     __hip_atomic_store(&K.ctl->err, (int64_t)1, __ATOMIC_RELAXED,
@@ -1044,30 +1068,77 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int64_t *do
         wait_for((ty + 1) % NTy, tx);
         wait_for(ty, (tx + NT - 1) % NT);
         wait_for(ty, (tx + 1) % NT);
-        wait_for(ty, tx);  // the palindrome's second visit waits for the first
+        wait_for(ty, tx);  // its own previous visit
+        // the values the polls observed were published by release stores:
+        // this fence orders the visit's reads after those visits' writes
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __builtin_amdgcn_wave_barrier();
+    Dom *dm = K.dom + rp.dom_off + d;
     const VisitOut o = visit_domain<MT, SCORE, WRAP>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
-        (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+        (uint32_t)vis, w, (uint32_t)rho, K.seed, dm, lds);
     if (__lane_id() == 0) {
         if (o.events) {
-            atomicAdd((unsigned long long *)&K.acc[rho].M, (unsigned long long)o.dM);
-            atomicAdd((unsigned long long *)&K.acc[rho].B, (unsigned long long)o.dB);
-            atomicAdd((unsigned long long *)&K.acc[rho].events,
-                      (unsigned long long)o.events);
+            int64_t *a = K.flow_acc + ((int64_t)g * K.n_rep + rho) * 3;
+            atomicAdd((unsigned long long *)&a[0], (unsigned long long)o.dM);
+            atomicAdd((unsigned long long *)&a[1], (unsigned long long)o.dB);
+            atomicAdd((unsigned long long *)&a[2], (unsigned long long)o.events);
+        }
+        if (vis + 1 == rp.visits) {  // the domain's clock at the end of sweep w
+            double *ck = K.flow_clk + ((int64_t)g * K.n_dom_total + rp.dom_off + d) * 2;
+            ck[0] = dm->clk_sum;
+            ck[1] = dm->clk_comp;
         }
         if constexpr (SCORE) {
-            const int64_t bin = K.ctl->run_done / K.ctl->rec_every;
-            double *b = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
-            atomicAdd(b, o.sJ);
-            atomicAdd(b + 1, o.sh);
+            const int64_t bin = run_done / K.ctl->rec_every;
+            double *bb = K.bins + ((int64_t)rho * K.n_bins + bin) * 2;
+            atomicAdd(bb, o.sJ);
+            atomicAdd(bb + 1, o.sh);
         }
         // this domain's visits so far in sweep w (the palindrome's second
         // visit has vis = 1)
         __hip_atomic_store(dn + d, base + (int64_t)vis + 1,
                            __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// After a dataflow launch of G sweeps: one wavefront per replica adds the
+// sweeps' changes to the running totals in sweep order and writes the
+// records that fall due, with the replica time from the clock snapshots
+// (the same fixed-order mean as replica_time).
+__global__ __launch_bounds__(64) void k_flow_close(KParams K, int G) {
+    const int rho = blockIdx.x;
+    const Ctl c = *K.ctl;
+    const Rep rp = K.reps[rho];
+    const int lane = __lane_id();
+    RepAcc acc = K.acc[rho];
+    for (int g = 0; g < G; ++g) {
+        const int64_t *a = K.flow_acc + ((int64_t)g * K.n_rep + rho) * 3;
+        acc.M += a[0];
+        acc.B += a[1];
+        acc.events += a[2];
+        const int64_t done = c.run_done + g + 1;
+        if (!K.write_records || done % c.rec_every) continue;
+        double s = 0.0, cpen = 0.0;
+        for (int dd = lane; dd < rp.ND; dd += 64) {
+            const double *ck = K.flow_clk + ((int64_t)g * K.n_dom_total + rp.dom_off + dd) * 2;
+            neumaier_add(s, cpen, ck[0] + ck[1]);
+        }
+        const double t = wave_sum_f64(s + cpen) / (double)rp.ND;
+        if (lane == 0) {
+            const int64_t k = c.rec_base + done / c.rec_every - 1;
+            Record r;
+            r.sweep = c.sweep + g + 1;
+            r.M = acc.M;
+            r.B = acc.B;
+            r.events = acc.events;
+            r.steps = (c.sweep + g + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
+            r.t = t;
+            K.rec[k * K.n_rep + rho] = r;
+        }
+    }
+    if (lane == 0) K.acc[rho] = acc;
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {

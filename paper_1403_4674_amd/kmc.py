@@ -23,6 +23,7 @@ F_CHECKPOINT, F_PERSISTENT, F_GRAPH, F_NO_MULTI, F_DEVICE_OUT, F_MULTI, F_SCORE,
     0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80)
 F_FLOW = 0x100
 F_RESIDENT = 0x200
+FLOW_MAX_SWEEPS = 64  # sweeps of one dataflow launch (KMC_F_FLOW)
 
 STATUS_NAMES = {0: "KMC_OK", -1: "KMC_EINVAL", -2: "KMC_ENOMEM", -3: "KMC_EDEVICE",
                 -4: "KMC_ESTATE", -5: "KMC_EUNSUPPORTED"}

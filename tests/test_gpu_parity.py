@@ -250,6 +250,37 @@ def test_one_launch_sweeps_are_bit_identical(torch_cuda, oracle_lib, graph):
         assert_replica_equal(b, rho, o, rb[rho], orec, f"flow replica {rho}")
 
 
+def test_dataflow_windows_of_many_sweeps(torch_cuda, oracle_lib):
+    """Runs longer than one dataflow launch (64 sweeps): sweeps of a window
+    overlap, records every 7 sweeps straddle the window boundaries, and the
+    result still equals the phase launches bit for bit (records, lattices,
+    per-domain clocks); the fused score over the windows matches the phase
+    form's within the score tolerance."""
+    descs = FLOW_MIX[:4] + [FLOW_MIX[6]]
+    say("dataflow windows: 150 sweeps, records every 7")
+    a = kmc.Lattice(descs, 91)
+    b = kmc.Lattice(descs, 91)
+    a.run(150, 7)
+    b.run(150, 7, kmc.F_FLOW | kmc.F_TIMING)
+    ms, n = b.timing()
+    assert n == 3 and ms > 0  # 64 + 64 + 22 sweeps
+    assert np.array_equal(a.records(), b.records())
+    for rho in range(len(descs)):
+        assert np.array_equal(a.spins(rho), b.spins(rho)), rho
+        for x, y in zip(a.domain_state(rho), b.domain_state(rho)):
+            assert np.array_equal(x, y), rho
+    o = oracle_for(oracle_lib, descs[2], 91, 2)
+    assert_records_equal(b.records()[2], o.run(150, 7), "oracle")
+    say("dataflow windows: fused score, 130 sweeps")
+    a.run(130, 10, kmc.F_SCORE)
+    b.run(130, 10, kmc.F_FLOW | kmc.F_SCORE)
+    sa, sb = a.score(13), b.score(13)
+    assert np.array_equal(a.records(), b.records())
+    for rho, d in enumerate(descs):
+        ticks = 10 * d["L"] ** 2 * (2 if d.get("schedule") else 1)
+        np.testing.assert_allclose(sb[rho], sa[rho], rtol=1e-10, atol=1e-11 * ticks)
+
+
 @pytest.mark.parametrize("which", ["1024", "4096"])
 def test_one_launch_sweeps_full_shapes(torch_cuda, oracle_lib, which):
     if which == "1024":
@@ -262,7 +293,7 @@ def test_one_launch_sweeps_full_shapes(torch_cuda, oracle_lib, which):
     say(f"one-launch sweeps on {which}^2, {sweeps} sweeps")
     lat, g, oras, o = run_both(oracle_lib, descs, seed, sweeps, 1, kmc.F_FLOW | kmc.F_TIMING)
     ms, n = lat.timing()
-    assert n == sweeps and ms > 0
+    assert n == -(-sweeps // kmc.FLOW_MAX_SWEEPS) and ms > 0  # sweeps share launches
     assert_replica_equal(lat, 0, oras[0], g[0], o[0], f"flow {which}")
 
 
