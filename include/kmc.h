@@ -145,6 +145,23 @@ typedef void (*kmc_free_fn)(void *ptr, void *user);
 kmc_status kmc_set_device_allocator(kmc_alloc_fn alloc, kmc_free_fn free_fn,
                                     void *user);
 
+/* Exact propagation (Sec. 3.1: reference values from evolving the
+ * probability vector with Eq. (CK_parallel in s)) of one replica's
+ * distribution over all 2^(L*L) spin configurations through n_sweeps sweeps
+ * of the parallel transition matrix T_PAR: the uniform mixture over all
+ * orders of the colours (Eq. (sum of sequential tms); at most 4 colours,
+ * else KMC_EUNSUPPORTED), or the palindrome.  State index s: bit y*L + x set
+ * when spin (y, x) is +1.  p: device array of 2^(L*L) doubles, the start
+ * distribution in, the result out; work: device array of 3 * 2^(L*L)
+ * doubles (caller-owned scratch; the call allocates nothing).  L*L <= 26;
+ * the descriptor's init and seed play no part.  Flags: KMC_EXACT_QUANTISED
+ * uses the Q32 rates the kMC path flips with (else the real w).  Enqueued on
+ * hip_stream (NULL: the null stream); asynchronous.  A verification tool:
+ * state histograms of many replicas can be compared with it. */
+#define KMC_EXACT_QUANTISED 0x1u
+kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
+                            int64_t n_sweeps, uint32_t flags, void *hip_stream);
+
 /* Per-class rate table of one replica (Appendix A, Eq. (Glauber_TM)).
  * Class c = 5*[s=+1] + k, k = number of up neighbours (0..4), flip energy
  * dE = 2 s (J (2k-4) + h).  r[c] = min(2^32, floor(w 2^32 + 1/2)) is the Q32

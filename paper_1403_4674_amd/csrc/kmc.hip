@@ -18,6 +18,7 @@
 #include "kmc_device.h"
 #include "kmc_multi.h"
 #include "kmc_resident.h"
+#include "kmc_exact.h"
 
 using kmcdev::Ctl;
 using kmcdev::MItem;
@@ -628,6 +629,88 @@ extern "C" kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_
                                      double gh[10]) {
     if (!r || !w || !gJ || !gh) return KMC_EINVAL;
     return rate_table(J, h, T, rate_model, r, w, gJ, gh);
+}
+
+extern "C" kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
+                                       int64_t n_sweeps, uint32_t flags, void *hip_stream) {
+    if (!d || !p || !work || n_sweeps < 0) return KMC_EINVAL;
+    try {
+        validate(nullptr, *d, 0);
+        const int L = d->L, N = L * L;
+        if (N > kmcdev::kExactMaxSites) return KMC_EINVAL;
+        const int Bx = d->tile, By = tile_rows_of(*d), NTx = L / Bx, NTy = L / By;
+        const int cx = axis_colours(NTx), ncol = cx * axis_colours(NTy);
+        const bool pal = d->schedule == KMC_SCHED_PALINDROME;
+        if (!pal && ncol > 4) return KMC_EUNSUPPORTED;  // more than 4! orders to mix
+        uint64_t r[10];
+        double w[10], gJ[10], gh[10];
+        if (rate_table(d->J, d->h, d->T, d->rate_model, r, w, gJ, gh) != KMC_OK)
+            return KMC_EINVAL;
+        kmcdev::ExactRates R;
+        for (int c = 0; c < 10; ++c)
+            R.w[c] = (flags & KMC_EXACT_QUANTISED) ? (double)r[c] * 0x1p-32 : w[c];
+        // domains (row-major over the grid, sites row-major inside) by colour
+        auto axis_colour = [](int t, int n) { return n == 1 ? 0 : (n % 2 && t == n - 1) ? 2 : t % 2; };
+        std::vector<std::vector<kmcdev::ExactDomain>> by_colour(ncol);
+        for (int ty = 0; ty < NTy; ++ty)
+            for (int tx = 0; tx < NTx; ++tx) {
+                kmcdev::ExactDomain D;
+                std::memset(&D, 0, sizeof(D));
+                D.n = Bx * By;
+                for (int ly = 0; ly < By; ++ly)
+                    for (int lx = 0; lx < Bx; ++lx) {
+                        const int a = ly * Bx + lx, y = ty * By + ly, x = tx * Bx + lx;
+                        D.site[a] = y * L + x;
+                        D.nb[a][0] = ((y + L - 1) % L) * L + x;
+                        D.nb[a][1] = ((y + 1) % L) * L + x;
+                        D.nb[a][2] = y * L + (x + L - 1) % L;
+                        D.nb[a][3] = y * L + (x + 1) % L;
+                    }
+                by_colour[axis_colour(tx, NTx) + cx * axis_colour(ty, NTy)].push_back(D);
+            }
+        // colour orders: all of them (mixed uniformly) or the palindrome
+        std::vector<std::vector<int>> orders;
+        if (pal) {
+            std::vector<int> o;
+            for (int k = 0; k < ncol; ++k) o.push_back(k);
+            for (int k = ncol - 1; k >= 0; --k) o.push_back(k);
+            orders.push_back(o);
+        } else {
+            std::vector<int> o(ncol);
+            for (int k = 0; k < ncol; ++k) o[k] = k;
+            do orders.push_back(o); while (std::next_permutation(o.begin(), o.end()));
+        }
+        const int NI = d->steps_per_visit ? d->steps_per_visit : Bx * By;
+        const int64_t n = (int64_t)1 << N;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+        double *acc = work, *b0 = work + n, *b1 = work + 2 * n;
+        const double inv_nd = 1.0 / (double)(Bx * By);
+        auto run_order = [&](const std::vector<int> &o, const double *src) -> double * {
+            double *cur = b0, *nxt = b1;
+            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, src, cur, n);
+            for (int col : o)
+                for (const kmcdev::ExactDomain &D : by_colour[col])
+                    for (int t = 0; t < NI; ++t) {
+                        hipLaunchKernelGGL(kmcdev::k_exact_tick, dim3(grid), dim3(256), 0, st,
+                                           cur, nxt, n, D, R, inv_nd);
+                        std::swap(cur, nxt);
+                    }
+            return cur;
+        };
+        for (int64_t sw = 0; sw < n_sweeps; ++sw) {
+            for (size_t k = 0; k < orders.size(); ++k) {
+                const double *res = run_order(orders[k], p);
+                hipLaunchKernelGGL(kmcdev::k_exact_axpy, dim3(grid), dim3(256), 0, st, acc, res,
+                                   1.0 / (double)orders.size(), n, k == 0 ? 1 : 0);
+            }
+            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, acc, p, n);
+        }
+        if (hipGetLastError() != hipSuccess) return KMC_EDEVICE;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
 }
 
 extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,

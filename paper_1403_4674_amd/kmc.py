@@ -73,6 +73,7 @@ def lib():
             "kmc_get_domain_state": ([P, I32, P, P, P], I32),
             "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
             "kmc_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], I32),
+            "kmc_exact_sweeps": ([C.POINTER(ReplicaDesc), P, P, I64, C.c_uint32, P], I32),
             "kmc_last_error": ([P], C.c_char_p),
             "kmc_destroy": ([P], None),
         }
@@ -90,7 +91,7 @@ def exported_symbols():
     names = ["kmc_set_device_allocator", "kmc_rate_table", "kmc_init_lattice",
              "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
              "kmc_get_domain_state", "kmc_get_info", "kmc_get_timing", "kmc_last_error",
-             "kmc_destroy"]
+             "kmc_destroy", "kmc_exact_sweeps"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -143,6 +144,27 @@ def make_descs(descs):
                              int(d.get("init", INIT_RANDOM)),
                              int(d.get("tile_rows", 0)))
     return arr
+
+
+EXACT_QUANTISED = 0x1
+
+
+def kmc_exact_sweeps(desc, p, work, n_sweeps, quantised=True, stream=None):
+    """Exact propagation of a distribution over the 2^(L*L) configurations of
+    one replica (desc: a descriptor dict) through n_sweeps sweeps, in place
+    in p (a float64 CUDA tensor of 2^(L*L) entries); work: a float64 CUDA
+    tensor of 3 * 2^(L*L) entries.  Runs on torch's current stream."""
+    import torch
+    n = 1 << (int(desc["L"]) ** 2)
+    for t, size in ((p, n), (work, 3 * n)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() >= size):
+            raise ValueError("p and work must be contiguous float64 CUDA tensors of 2^N and 3 2^N")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    arr = make_descs([desc])
+    _check(lib().kmc_exact_sweeps(arr, C.c_void_p(p.data_ptr()), C.c_void_p(work.data_ptr()),
+                                  int(n_sweeps), EXACT_QUANTISED if quantised else 0,
+                                  C.c_void_p(stream) if stream else None))
 
 
 def kmc_init_lattice(descs, seed, given_spins=None, stream=None):

@@ -1,0 +1,142 @@
+"""Exact propagation of state distributions on the GPU (kmc_exact_sweeps;
+needs an MI355X).
+
+* Equal to the oracle's exact tool (oracle/exact.py, numpy over 2^N states)
+  after a few sweeps on every partition shape, schedule and rate model, with
+  and without the Q32 rate quantisation.
+* At 5 x 5 (2^25 states, beyond what the numpy tool reaches in seconds):
+  probability is conserved and the Boltzmann distribution is stationary
+  (Eq. (general reversibility condition)) for the unpartitioned lattice and
+  for the 25 one-site domains (9 colours, palindrome).
+* The kMC path at scale against it: the joint (M, B) histogram of 200 000
+  replicas of a 4 x 4 lattice run by the batched persistent kernel after two
+  sweeps from the all-up start matches the exact (quantised) distribution
+  (chi-square).
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import exact
+from paper_1403_4674_amd import kmc
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def gpu_exact(torch, desc, p0, sweeps, quantised):
+    n = p0.size
+    p = torch.tensor(p0, dtype=torch.float64, device="cuda")
+    work = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    kmc.kmc_exact_sweeps(desc, p, work, sweeps, quantised=quantised)
+    torch.cuda.synchronize()
+    return p.cpu().numpy()
+
+
+SYSTEMS = [
+    # desc, sweeps
+    (dict(L=4, tile=2, T=2.5, h=0.1, steps_per_visit=4), 2),
+    (dict(L=4, tile=2, tile_rows=4, T=2.0, h=-0.2, steps_per_visit=3,
+          rate_model=kmc.RATE_BARKER), 2),
+    (dict(L=4, tile=2, T=2.3, steps_per_visit=2, schedule=kmc.SCHED_PALINDROME), 2),
+    (dict(L=3, tile=3, T=2.0, h=0.1, steps_per_visit=9), 3),
+    (dict(L=3, tile=1, tile_rows=3, T=2.4, steps_per_visit=2,
+          rate_model=kmc.RATE_BARKER), 2),
+    (dict(L=4, tile=1, T=3.0, h=0.2, steps_per_visit=1), 2),
+    (dict(L=4, tile=4, tile_rows=2, T=2.2, steps_per_visit=5), 1),
+    (dict(L=3, tile=1, T=2.5, steps_per_visit=1, schedule=kmc.SCHED_PALINDROME), 1),
+]
+
+
+@pytest.mark.parametrize("quantised", [True, False])
+@pytest.mark.parametrize("k", range(len(SYSTEMS)))
+def test_exact_equals_the_oracle_tool(torch_cuda, k, quantised):
+    d, sweeps = SYSTEMS[k]
+    say(f"exact propagation {d} quantised={quantised}")
+    L = d["L"]
+    rng = np.random.default_rng(k)
+    p0 = rng.random(1 << (L * L))
+    p0 /= p0.sum()
+    op = exact.SweepOperator(L, d["tile"], d.get("J", 1.0), d.get("h", 0.0), d["T"],
+                             d.get("rate_model", 0), d["steps_per_visit"], quantise=quantised,
+                             palindrome=d.get("schedule", 0) == 1, By=d.get("tile_rows"))
+    ref = p0
+    for _ in range(sweeps):
+        ref = op.par(ref)
+    got = gpu_exact(torch_cuda, d, p0, sweeps, quantised)
+    assert np.abs(got - ref).max() < 1e-14
+    assert abs(got.sum() - 1.0) < 1e-13
+
+
+def boltzmann_gpu(torch, L, J, h, T):
+    """pi over the 2^(L L) states, computed with torch on the device."""
+    N = L * L
+    s = torch.arange(1 << N, device="cuda", dtype=torch.int64)
+    spin = lambda i: ((s >> i) & 1).to(torch.float64) * 2 - 1
+    M = torch.zeros(1 << N, dtype=torch.float64, device="cuda")
+    B = torch.zeros_like(M)
+    for y in range(L):
+        for x in range(L):
+            a = spin(y * L + x)
+            M += a
+            B += a * spin(y * L + (x + 1) % L) + a * spin(((y + 1) % L) * L + x)
+    lw = (J * B + h * M) / T
+    w = torch.exp(lw - lw.max())
+    return w / w.sum()
+
+
+@pytest.mark.parametrize("d", [
+    dict(L=5, tile=5, T=2.3, h=0.1, steps_per_visit=25),
+    dict(L=5, tile=1, T=2.6, h=-0.05, steps_per_visit=1, schedule=kmc.SCHED_PALINDROME,
+         rate_model=kmc.RATE_BARKER),
+])
+def test_boltzmann_is_stationary_at_5x5(torch_cuda, d):
+    torch = torch_cuda
+    say(f"exact 5x5 stationarity {d}")
+    pi = boltzmann_gpu(torch, 5, d.get("J", 1.0), d["h"], d["T"])
+    p = pi.clone()
+    work = torch.empty(3 * p.numel(), dtype=torch.float64, device="cuda")
+    kmc.kmc_exact_sweeps(d, p, work, 1, quantised=False)
+    torch.cuda.synchronize()
+    assert abs(float(p.sum()) - 1.0) < 1e-12
+    assert float((p - pi).abs().max()) < 1e-12 * float(pi.max())
+    # a start far from equilibrium moves towards it
+    q = torch.zeros_like(pi)
+    q[-1] = 1.0  # all up
+    kmc.kmc_exact_sweeps(d, q, work, 3, quantised=False)
+    torch.cuda.synchronize()
+    assert abs(float(q.sum()) - 1.0) < 1e-12 and float(q.min()) >= 0.0
+
+
+def test_kmc_histogram_matches_exact_distribution(torch_cuda):
+    torch = torch_cuda
+    d = dict(L=4, tile=2, T=2.5, h=0.1, steps_per_visit=4, init=kmc.INIT_ALL_UP)
+    n_rep, sweeps = 200_000, 2
+    say("200000 replicas of 4x4 against the exact distribution")
+    lat = kmc.Lattice([d] * n_rep, 2024)
+    lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
+    rec = lat.records()[:, -1]
+    lat.close()
+    p0 = np.zeros(1 << 16)
+    p0[-1] = 1.0
+    p = gpu_exact(torch, d, p0, sweeps, quantised=True)
+    M, B = exact.magnetisation_and_bonds(4)
+    keys = (M + 16) * 100 + (B + 32)
+    uniq, inv = np.unique(keys, return_inverse=True)
+    prob = np.bincount(inv, weights=p, minlength=uniq.size)
+    obs_keys = (rec["M"] + 16) * 100 + (rec["B"] + 32)
+    pos = np.searchsorted(uniq, obs_keys)
+    assert np.array_equal(uniq[pos], obs_keys)  # every observed (M, B) is possible
+    counts = np.bincount(pos, minlength=uniq.size).astype(float)
+    exp_ = prob * n_rep
+    big = exp_ >= 5
+    obs = np.append(counts[big], counts[~big].sum())
+    ex = np.append(exp_[big], exp_[~big].sum())
+    assert stats.chisquare(obs, ex * obs.sum() / ex.sum()).pvalue > 1e-5
