@@ -135,3 +135,38 @@ def test_study_settings_cover_the_papers_partitions():
         "stripes N_D=2", "stripes N_D=4", "checkerboard N_D=4", "checkerboard N_D=16"}
     huge = experiments.settings_2d(256)  # beyond the resident form: domains <= 64
     assert all(By <= 64 and Bx <= 64 for _, Bx, By, _ in huge)
+
+
+def test_autocorrelation_and_tau_against_exact_propagation(oracle_lib):
+    """The analysis on sampled trajectories against the exact equilibrium
+    autocorrelation of A = H m for the unpartitioned 3 x 3 lattice (Barker,
+    1/(beta J) = 2.4, h = 0.15, one sweep = 9 steps): C(k) = A . T^k (pi A) - <A>^2
+    with T the exact sweep operator (oracle/exact.py).  Trajectories come
+    from the oracle, started from exact Boltzmann samples."""
+    from oracle import exact
+    L, T, NI, h = 3, 2.4, 9, 0.15  # a field: <A> != 0, so the connected part matters
+    pi, M, B, _ = exact.boltzmann(L, 1.0, h, T)
+    A = ((-B - h * M) / 9.0) * (M / 9.0)
+    op = exact.SweepOperator(L, L, 1.0, h, T, model=1, NI=NI, quantise=True)
+    v = pi * A
+    mean = float(pi @ A)
+    C_exact = []
+    for _ in range(13):
+        C_exact.append(float(A @ v) - mean * mean)
+        v = op.par(v)
+    C_exact = np.array(C_exact)
+    rng = np.random.default_rng(5)
+    n_traj, n_sw = 240, 2500
+    starts = rng.choice(pi.size, size=n_traj, p=pi)
+    traj = []
+    for rep, i in enumerate(starts):
+        spins = np.where((i >> np.arange(L * L)) & 1, 1, -1).astype(np.int8)
+        r = oracle_lib.Replica(L, L, T=T, h=h, rate_model=1, steps_per_visit=NI,
+                               init=oracle_lib.INIT_GIVEN, spins=spins, seed=77, replica=rep)
+        traj.append(r.run(n_sw, 1))
+    rec = np.array(traj)
+    Am = analysis.observable(rec, L, h=h, kind="Hm")
+    C = analysis.autocorrelation(Am, 12)
+    np.testing.assert_allclose(C / C[0], C_exact / C_exact[0], atol=0.03)
+    t_hat, t_exact = analysis.fit_tau(C, NI), analysis.fit_tau(C_exact, NI)
+    assert t_hat == pytest.approx(t_exact, rel=0.08)
