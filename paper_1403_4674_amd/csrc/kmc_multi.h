@@ -250,7 +250,10 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // rate class and member index (class lanes of each slot; the
             // FP64 index is exact, see visit_domain)
             const uint32_t cseg_c = seg16(__ballot(xe < Pinc), slot);
-            const int c = __builtin_ctz(cseg_c | 0x10000u);
+            // an active slot always finds its class at or below lane 9 (lane 9
+            // holds R > xe); an idle slot gets 9 too, so every class-indexed
+            // shift below stays in range (its results are discarded)
+            const int c = __builtin_ctz(cseg_c | 0x200u);
             const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
             const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
             const uint32_t j = sbc32(jl, base + c);
