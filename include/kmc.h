@@ -145,6 +145,14 @@ typedef void (*kmc_free_fn)(void *ptr, void *user);
 kmc_status kmc_set_device_allocator(kmc_alloc_fn alloc, kmc_free_fn free_fn,
                                     void *user);
 
+/* Bound, in polls, of each wait of the dataflow sweeps (KMC_F_FLOW) of this
+ * context; default 2^24 (seconds).  For callers that test the failure path:
+ * a wait that exceeds it gives up, the run is reported as failed
+ * (KMC_EDEVICE from kmc_observables, or from kmc_backward_score for a replay
+ * with host output), and the context's results stay void from then on.
+ * max_polls < 0: KMC_EINVAL. */
+kmc_status kmc_set_wait_limit(kmc_ctx *c, int64_t max_polls);
+
 /* Exact propagation (Sec. 3.1: reference values from evolving the
  * probability vector with Eq. (CK_parallel in s)) of one replica's
  * distribution over all 2^(L*L) spin configurations through n_sweeps sweeps

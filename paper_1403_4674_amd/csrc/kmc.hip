@@ -86,6 +86,7 @@ struct kmc_ctx {
     Ctl *d_ctl = nullptr;
     int64_t *d_done = nullptr;  // per-domain visit counters of the one-launch sweeps
     // per-sweep slots of a dataflow launch (allocated on first use)
+    int64_t flow_max_polls = kmcdev::kFlowMaxPolls;  // bound of each dataflow wait
     int64_t *d_flow_acc = nullptr;  // [kFlowMaxSweeps][n_rep][3]
     double *d_flow_clk = nullptr;   // [kFlowMaxSweeps][n_dom][2]
     bool graph_flow = false;    // the cached phase graph was captured with flow
@@ -313,6 +314,7 @@ KParams params(kmc_ctx *c) {
     K.flow_acc = c->d_flow_acc;
     K.flow_clk = c->d_flow_clk;
     K.n_dom_total = c->n_dom;
+    K.flow_max_polls = c->flow_max_polls;
     return K;
 }
 
@@ -601,10 +603,12 @@ int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * d.L; }
 
 // A one-launch sweep whose bounded wait gave up leaves ctl->err set (a
 // dependency never satisfied): the results of the run are not valid.
-void check_flow_error(kmc_ctx *c) {
+// A dataflow wait that gave up leaves the flag set for good: visits after
+// it may have read a halo out of order, so the context's results are void.
+void check_flow_error(kmc_ctx *c, const Ctl *ctl) {
     Ctl h;
-    hip_check(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl copy");
-    if (h.err) fail(c, KMC_EDEVICE, "a one-launch sweep timed out waiting for a neighbour");
+    hip_check(c, hipMemcpy(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl copy");
+    if (h.err) fail(c, KMC_EDEVICE, "a dataflow sweep timed out waiting for a neighbour");
 }
 
 void destroy_buffers(kmc_ctx *c) {
@@ -629,6 +633,21 @@ extern "C" kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_
                                      double gh[10]) {
     if (!r || !w || !gJ || !gh) return KMC_EINVAL;
     return rate_table(J, h, T, rate_model, r, w, gJ, gh);
+}
+
+extern "C" kmc_status kmc_set_wait_limit(kmc_ctx *c, int64_t max_polls) {
+    if (!c) return KMC_EINVAL;
+    if (max_polls < 0) {
+        c->err = "max_polls must be >= 0";
+        return KMC_EINVAL;
+    }
+    c->flow_max_polls = max_polls;
+    // captured graphs hold the old bound in their kernel arguments
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
+    c->pgraph = nullptr;
+    return KMC_OK;
 }
 
 extern "C" kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
@@ -1089,7 +1108,7 @@ extern "C" kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capac
         hip_check(c, hipMemcpyAsync(h.data(), c->d_rec, sizeof(Record) * h.size(),
                                     hipMemcpyDeviceToHost, c->stream), "record copy");
         hip_check(c, hipStreamSynchronize(c->stream), "record sync");
-        check_flow_error(c);
+        check_flow_error(c, c->d_ctl);
         for (int rho = 0; rho < c->n_rep; ++rho)
             for (int64_t k = 0; k < n; ++k)
                 std::memcpy(&out[rho * capacity + k], &h[k * c->n_rep + rho], sizeof(Record));
@@ -1148,6 +1167,8 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         K.bins = c->d_bins;
         K.n_bins = (int32_t)n_bins;
         K.write_records = 0;
+        // each replay starts from the checkpoint with a clear error flag
+        hip_check(c, hipMemsetAsync(c->r_ctl, 0, sizeof(Ctl), s), "replay ctl");
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
         if (c->ck_flags & KMC_F_RESIDENT) {
@@ -1168,8 +1189,10 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
                                       (size_t)n_bins * 2 * sizeof(double),
                                       (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind, s),
                   "score copy");
-        if (!(flags & KMC_F_DEVICE_OUT))
+        if (!(flags & KMC_F_DEVICE_OUT)) {
             hip_check(c, hipStreamSynchronize(s), "score sync");
+            if (c->ck_flags & KMC_F_FLOW) check_flow_error(c, c->r_ctl);
+        }
     } catch (const Fail &f) {
         return f.st;
     }

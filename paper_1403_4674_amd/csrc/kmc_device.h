@@ -117,6 +117,7 @@ struct KParams {
     int64_t *flow_acc;
     double *flow_clk;
     int32_t n_dom_total;      // domain records of all replicas
+    int64_t flow_max_polls;   // bound of each wait of the dataflow sweeps
 };
 
 // ------------------------------------------------------------------ Philox
@@ -994,7 +995,7 @@ __device__ inline int visits_before(const Rep &rp, uint64_t pos_of, int col, int
     return (int)((pos_of >> (4 * col)) & 15u) < p ? 1 : 0;
 }
 
-constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;
+constexpr int64_t kFlowMaxPolls = int64_t(1) << 24;  // default bound of a wait
 constexpr int kFlowMaxSweeps = 64;  // sweeps of one dataflow launch
 
 // G whole sweeps of the phase-by-phase form in one launch.  Block b runs
@@ -1014,8 +1015,9 @@ constexpr int kFlowMaxSweeps = 64;  // sweeps of one dataflow launch
 // colours, domains whose neighbours finished early, and the next sweep's
 // early visits run ahead.  Blocks are numbered sweep- and phase-major, so a
 // block only waits on blocks numbered before it.  A wait that exceeds
-// kFlowMaxPolls polls sets ctl->err and gives up (the host reports the run
-// as failed), so no wave can hang.  Sweeps overlap, so a visit adds its
+// K.flow_max_polls polls (kFlowMaxPolls unless the host sets another bound)
+// sets ctl->err and gives up (the host reports the run as failed), so no wave
+// can hang.  Sweeps overlap, so a visit adds its
 // changes of M, B and events to its sweep's slot and stores its domain's
 // clock after the sweep's last visit; k_flow_close forms the records.
 template <typename MT, bool SCORE, bool WRAP>
@@ -1057,7 +1059,7 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
             // fence once every wait is over
             while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++polls > kFlowMaxPolls) {
+                if (++polls > K.flow_max_polls) {
                     __hip_atomic_store(&K.ctl->err, (int64_t)1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     return;

@@ -74,6 +74,7 @@ def lib():
             "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
             "kmc_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], I32),
             "kmc_exact_sweeps": ([C.POINTER(ReplicaDesc), P, P, I64, C.c_uint32, P], I32),
+            "kmc_set_wait_limit": ([P, I64], I32),
             "kmc_last_error": ([P], C.c_char_p),
             "kmc_destroy": ([P], None),
         }
@@ -91,7 +92,7 @@ def exported_symbols():
     names = ["kmc_set_device_allocator", "kmc_rate_table", "kmc_init_lattice",
              "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
              "kmc_get_domain_state", "kmc_get_info", "kmc_get_timing", "kmc_last_error",
-             "kmc_destroy", "kmc_exact_sweeps"]
+             "kmc_destroy", "kmc_exact_sweeps", "kmc_set_wait_limit"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -273,6 +274,10 @@ class Lattice:
 
     def domain_state(self, replica=0):
         return kmc_get_domain_state(self.ctx, replica)
+
+    def set_wait_limit(self, max_polls):
+        """Bound of each dataflow wait (a hook for testing the failure path)."""
+        _check(lib().kmc_set_wait_limit(self.ctx, int(max_polls)), self.ctx)
 
     def timing(self):
         return kmc_get_timing(self.ctx)

@@ -93,7 +93,23 @@ def test_calls_reject_null_context(kmc):
     assert L.kmc_run_schedule(None, 1, 1, 0) == kmc.KMC_EINVAL
     assert L.kmc_backward_score(None, None, 0, 0) == kmc.KMC_EINVAL
     assert L.kmc_get_spins(None, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_set_wait_limit(None, 5) == kmc.KMC_EINVAL
     assert L.kmc_last_error(None) == b"null context"
+
+
+def test_exact_sweeps_rejects_bad_arguments(kmc):
+    """Validation happens before any device call (no GPU needed)."""
+    L = kmc.lib()
+    p = C.c_void_p(16)  # never dereferenced: every call below fails validation
+    big = kmc.make_descs([dict(L=6, tile=6, T=2.0)])          # 36 sites > 26
+    assert L.kmc_exact_sweeps(big, p, p, 1, 0, None) == kmc.KMC_EINVAL
+    bad = kmc.make_descs([dict(L=4, tile=3, T=2.0)])          # L not a multiple of tile
+    assert L.kmc_exact_sweeps(bad, p, p, 1, 0, None) == kmc.KMC_EINVAL
+    nine = kmc.make_descs([dict(L=3, tile=1, T=2.0)])         # 9 colours, random orders
+    assert L.kmc_exact_sweeps(nine, p, p, 1, 0, None) == kmc.KMC_EUNSUPPORTED
+    ok = kmc.make_descs([dict(L=4, tile=2, T=2.0)])
+    assert L.kmc_exact_sweeps(ok, None, p, 1, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_exact_sweeps(ok, p, p, -1, 0, None) == kmc.KMC_EINVAL
     L.kmc_destroy(None)
 
 

@@ -316,3 +316,31 @@ def test_one_launch_rejects_persistent(torch_cuda):
     with pytest.raises(kmc.KmcError) as e:
         lat.run(2, 1, kmc.F_FLOW | kmc.F_PERSISTENT)
     assert e.value.status == kmc.KMC_EINVAL
+
+
+def test_dataflow_wait_timeout_is_reported(torch_cuda):
+    """The failure path, forced from the host: with a bound of 0 polls every
+    wait that finds a neighbour unfinished gives up at once, so the launch
+    still ends, and the run is reported as failed (and stays so); a fresh
+    context with the default bound runs clean.  A replay that times out is
+    reported by kmc_backward_score; the forward run's records stay valid."""
+    d = [dict(L=128, tile=16, T=2.3, steps_per_visit=256)]
+    say("dataflow wait timeout")
+    lat = kmc.Lattice(d, 3)
+    lat.set_wait_limit(0)
+    lat.run(40, 40, kmc.F_FLOW)
+    for _ in range(2):
+        with pytest.raises(kmc.KmcError) as e:
+            lat.records()
+        assert e.value.status == kmc.KMC_EDEVICE
+    lat.close()
+    ok = kmc.Lattice(d, 3)
+    ok.run(40, 40, kmc.F_FLOW)
+    assert ok.records().shape == (1, 1)
+    ok.run(40, 20, kmc.F_FLOW | kmc.F_CHECKPOINT)
+    ok.set_wait_limit(0)
+    with pytest.raises(kmc.KmcError) as e:
+        ok.score(2)
+    assert e.value.status == kmc.KMC_EDEVICE
+    assert ok.records().shape == (1, 3)
+    ok.close()
