@@ -525,15 +525,18 @@ struct ClassSel {
     uint32_t xS, x0, x1, x2;
 };
 
-__device__ __forceinline__ uint32_t sgpr_sign_bit(uint32_t table, uint32_t c) {
+// The table is an immediate of the instruction (a literal, or an inline
+// constant), so no register is spent on it in the chain.
+template <uint32_t TABLE>
+__device__ __forceinline__ uint32_t sgpr_sign_bit(uint32_t c) {
     uint32_t r;
-    asm("s_bfe_i32 %0, %1, %2" : "=s"(r) : "s"(table), "s"(c | 0x10000u) : "scc");
+    asm("s_bfe_i32 %0, %1, %2" : "=s"(r) : "i"(TABLE), "s"(c | 0x10000u) : "scc");
     return r;
 }
 
 __device__ __forceinline__ ClassSel class_sel(int c) {
-    return ClassSel{sgpr_sign_bit(kInvS, (uint32_t)c), sgpr_sign_bit(kInvK0, (uint32_t)c),
-                    sgpr_sign_bit(kInvK1, (uint32_t)c), sgpr_sign_bit(kInvK2, (uint32_t)c)};
+    return ClassSel{sgpr_sign_bit<kInvS>((uint32_t)c), sgpr_sign_bit<kInvK0>((uint32_t)c),
+                    sgpr_sign_bit<kInvK1>((uint32_t)c), sgpr_sign_bit<kInvK2>((uint32_t)c)};
 }
 
 __device__ __forceinline__ uint32_t and_xor(uint32_t t, uint32_t v, uint32_t x) {
@@ -602,16 +605,21 @@ __device__ __forceinline__ uint32_t class_pos3(MT S, const Planes<MT> &P, int b)
     return q + 2u * q;
 }
 
-// Adds one (inc) or subtracts one (!inc) from the up-neighbour count k of
-// the sites in m, on the bit planes; no site overflows (k stays in 0..4).
+// Adds one (inv = 0) or subtracts one (inv = all ones) from the
+// up-neighbour count k of the sites in m, on the bit planes; no site
+// overflows (k stays in 0..4).
 template <typename MT>
-__device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
-    const MT inv = inc ? (MT)0 : ~(MT)0;
+__device__ __forceinline__ void planes_step_inv(Planes<MT> &P, MT m, MT inv) {
     const MT c1 = (P.s0 ^ inv) & m;
     const MT c2 = (P.s1 ^ inv) & c1;
     P.s0 ^= m;
     P.s1 ^= c1;
     P.s2 ^= c2;
+}
+
+template <typename MT>
+__device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
+    planes_step_inv<MT>(P, m, inc ? (MT)0 : ~(MT)0);
 }
 
 struct VisitOut {
@@ -761,29 +769,32 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                 rej = (uint32_t)mm < thr;
             }
         }
-        // x = slot 2^32 + w0, exact in a double
-        const double x = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x;
+        // x = slot 2^32 + w0, exact in a double, held as xh = x + 1/2: the
+        // comparisons with the integer sums R and P_c are unchanged by the
+        // half, and the member quotient below starts from it
+        const double xh = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x + 0.5;
         uint64_t left = __ballot(valid);  // ticks of the batch not yet decided
         double Rb = 0.0;                  // this lane's R before its event (0: none)
         int pos = 0;
         // the first undecided tick below R is the next event; the ticks
         // before it are nulls
-        uint64_t cand = __ballot(x < R) & left;
+        uint64_t cand = __ballot(xh < R) & left;
         while (cand) {
             const int e = __builtin_ctzll(cand);
             left &= ~1ull << e;  // drop the ticks up to and including e
             m_null += (uint32_t)(e - pos);
-            const double xe = rdl_f64(x, e);
+            const double xe = rdl_f64(xh, e);  // x_e + 1/2
             if (lane == e) Rb = R;
 
-            // rate class: first c with xe < P_c (lane 9 holds R > xe).  Member
-            // index j = floor((xe - P_{c-1}) / r_c), formed in every class lane
-            // at once as trunc((xe - P_{c-1} + 1/2) fl(1/r_c)): the quotient
-            // lies at least 1/(2 r_c) >= 2^-33 from an integer and the product
-            // is within 2^-39 of it (quotient < 2^13), so the truncation is
-            // exact.  Only lane c's quotient is read, then converted.
+            // rate class: first c with x_e < P_c (lane 9 holds R > x_e).
+            // Member index j = floor((x_e - P_{c-1}) / r_c), formed in every
+            // class lane at once as trunc((x_e + 1/2 - P_{c-1}) fl(1/r_c)): the
+            // quotient lies at least 1/(2 r_c) >= 2^-33 from an integer and
+            // the product is within 2^-39 of it (quotient < 2^13), so the
+            // truncation is exact.  Only lane c's quotient is read, then
+            // converted.
             const int c = __builtin_ctzll(__ballot(xe < Pinc));
-            const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
+            const double q = (xe - (Pinc - W)) * inv_lane;
             const uint32_t j = (uint32_t)rdl_f64(q, c);
 
             if constexpr (SCORE) {
@@ -815,19 +826,43 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             // column xs; the three rows are summed into row ys by DPP
             // neighbour rows and columns; outside the tile (-1 or B) they are
             // halo and frozen, unless the lattice is one periodic domain
-            const bool up = c >= 5;
-            const int c_new = up ? c - 5 : c + 5;
-            const int ym = ys - 1 + (ys == 0 ? wrapY : 0), yp = ys + 1 - (ys == By - 1 ? wrapY : 0);
-            const int xm = xs - 1 + (xs == 0 ? wrapX : 0), xp = xs + 1 - (xs == B - 1 ? wrapX : 0);
+            // upm: all ones when the flipped spin is +1 (c >= 5), whose
+            // neighbours then lose an up neighbour; the flipped site moves
+            // to class c -/+ 5 (tally field 3 c -/+ 15)
+            const uint32_t upm = sgpr_sign_bit<0x3E0>((uint32_t)c);
+            const int c3 = 3 * c;
+            const int c3_new = c3 + 15 - (int)(upm & 30u);
             const bool on_row = lane == ys;
-            const bool adj = (lane == ym || lane == yp) && lane < By;
             constexpr int NB = 8 * (int)sizeof(MT);
-            const int ca = on_row ? xm : xs;
-            const bool va = on_row ? xm >= 0 : adj;
-            const bool vb = on_row && xp < B;
-            const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
-            const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
-            uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+            int ym = ys - 1, yp = ys + 1, xm = xs - 1, xp = xs + 1;
+            bool adj;
+            MT nm = 0;    // this lane's neighbours of the flipped site
+            uint32_t nb;  // their classes as tallies
+            if constexpr (!WRAP) {
+                // row ys: columns xs -/+ 1 inside the tile; rows ys -/+ 1:
+                // column xs.  Each lane reads its sites at xa (xs - 1 on row
+                // ys, else xs) and xb = xs + 1; a column outside the tile, or
+                // not this lane's, is a clear bit of nm
+                const MT bx = (MT)1 << xs;
+                const MT mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+                adj = (lane == ym || lane == yp) && lane < By;
+                nm = on_row ? mrow : (adj ? bx : (MT)0);
+                const int xa = (xs - (on_row ? 1 : 0)) & (NB - 1), xb = (xs + 1) & (NB - 1);
+                const uint32_t va = (uint32_t)(nm >> xa) & 1u, vb = (uint32_t)(nm >> xb) & 1u;
+                nb = (va << class_pos3<MT>(S, P, xa)) + (vb << class_pos3<MT>(S, P, xb));
+            } else {
+                ym += ys == 0 ? wrapY : 0;
+                yp -= ys == By - 1 ? wrapY : 0;
+                xm += xs == 0 ? wrapX : 0;
+                xp -= xs == B - 1 ? wrapX : 0;
+                adj = (lane == ym || lane == yp) && lane < By;
+                const int ca = on_row ? xm : xs;
+                const bool va = on_row ? xm >= 0 : adj;
+                const bool vb = on_row && xp < B;
+                const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
+                const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
+                nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+            }
             uint32_t nb_s;
             if (wrapY == 0) {  // rows ys -/+ 1 are the neighbouring lanes
                 nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
@@ -837,9 +872,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             }
             // every neighbour moves one class up (flip to +1) or down: the
             // whole tally shifts by one field (no class leaves its spin's range)
-            const uint32_t sub_s = nb_s + (1u << (3 * c));
+            const uint32_t sub_s = nb_s + (1u << c3);
             const uint32_t add_s =
-                (uint32_t)(((uint64_t)nb_s << 3) >> (up ? 6 : 0)) + (1u << (3 * c_new));
+                (uint32_t)(((uint64_t)nb_s << 3) >> (upm & 6u)) + (1u << c3_new);
             n_lane = n_lane + ((add_s >> lane3) & 7u) - ((sub_s >> lane3) & 7u);
             ev_lane += lane == c ? 1u : 0u;
             W = (double)n_lane * rd_lane;
@@ -848,11 +883,14 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
 
             // flip, and move the neighbours' up-counts on the bit planes
             const MT bx = (MT)1 << xs;
-            const MT mrow = (xm >= 0 ? (MT)1 << xm : (MT)0) | (xp < B ? (MT)1 << xp : (MT)0);
+            if constexpr (WRAP) {
+                const MT mrow = (xm >= 0 ? (MT)1 << xm : (MT)0) | (xp < B ? (MT)1 << xp : (MT)0);
+                nm = on_row ? mrow : (adj ? bx : (MT)0);
+            }
             if (on_row) S ^= bx;
-            planes_step<MT>(P, on_row ? mrow : (adj ? bx : (MT)0), !up);
+            planes_step_inv<MT>(P, nm, (MT)(int64_t)(int32_t)upm);
             pos = e + 1;
-            cand = __ballot(x < R) & left;
+            cand = __ballot(xh < R) & left;
         }
         m_null += (uint32_t)__popcll(left);  // the batch's trailing nulls
         // residence times -ln(u)/R of this batch's events, kept per lane

@@ -230,21 +230,22 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
                 rej = (uint32_t)mm < thr;
             }
         }
-        const double x = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x;
+        // x + 1/2, as in visit_domain
+        const double xh = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x + 0.5;
         uint32_t left = seg16(__ballot(valid), slot);  // the slot's undecided ticks
         double Rb = 0.0;
         int pos = 0;
         for (;;) {
             // a slot without a further event in this batch adds its
             // remaining nulls once: its `left` is cleared below
-            const uint32_t cseg = seg16(__ballot(x < R), slot) & left;
+            const uint32_t cseg = seg16(__ballot(xh < R), slot) & left;
             if (!cseg) m_null += (uint32_t)__popc(left);
             const bool act = cseg != 0;
             if (!__ballot(act)) break;
             const int e = __builtin_ctz(cseg | 0x10000u);  // 16 when idle
             left &= ~(cseg ^ (cseg - 1u));
             if (act) m_null += (uint32_t)(e - pos);
-            const double xe = sbc_f64(x, base + e);
+            const double xe = sbc_f64(xh, base + e);
             if (act && sl == e) Rb = R;
 
             // rate class and member index (class lanes of each slot; the
@@ -254,7 +255,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // holds R > xe); an idle slot gets 9 too, so every class-indexed
             // shift below stays in range (its results are discarded)
             const int c = __builtin_ctz(cseg_c | 0x200u);
-            const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
+            const double q = (xe - (Pinc - W)) * inv_lane;
             const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
             const uint32_t j = sbc32(jl, base + c);
 
@@ -281,14 +282,17 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // neighbours, the three rows summed inside the slot by DPP
             const bool up = c >= 5;
             const int c_new = up ? c - 5 : c + 5;
+            // this lane's neighbours of the flipped site (nm, as in
+            // visit_domain): read at xa and xb, kept where nm has the bit
             const bool on_row = sl == ys;
             const bool adj = (sl == ys - 1 || sl == ys + 1) && sl < B;
-            const int ca = on_row ? xs - 1 : xs;
-            const bool va = on_row ? xs > 0 : adj;
-            const bool vb = on_row && xs < B - 1;
-            const uint32_t pa = class_pos3<uint32_t>(S, P, ca & 31);
-            const uint32_t pb = class_pos3<uint32_t>(S, P, (xs + 1) & 31);
-            uint32_t nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+            const uint32_t bx = 1u << xs;
+            const uint32_t mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+            const uint32_t nm = on_row ? mrow : (adj ? bx : 0u);
+            const int xa = (xs - (on_row ? 1 : 0)) & 31, xb = (xs + 1) & 31;
+            const uint32_t va = (nm >> xa) & 1u, vb = (nm >> xb) & 1u;
+            uint32_t nb = (va << class_pos3<uint32_t>(S, P, xa)) +
+                          (vb << class_pos3<uint32_t>(S, P, xb));
             nb += dppz<kRowShr + 1>(nb) + dppz<kRowShl1>(nb);
             const uint32_t nb_s = sbc32(nb, base + ys);
             const uint32_t sub_s = nb_s + (1u << (3 * c));
@@ -302,10 +306,8 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             Pinc = scan16_f64(W);
             R = rowbcast_f64<9>(Pinc);
 
-            const uint32_t bx = 1u << xs;
-            const uint32_t mrow = ((bx << 1) | (bx >> 1)) & vm_row;
             if (act && on_row) S ^= bx;
-            planes_step<uint32_t>(P, act ? (on_row ? mrow : (adj ? bx : 0u)) : 0u, !up);
+            planes_step<uint32_t>(P, act ? nm : 0u, !up);
             if (act) pos = e + 1;
         }
         if (Rb != 0.0) {

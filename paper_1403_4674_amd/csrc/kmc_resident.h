@@ -125,21 +125,22 @@ __device__ VisitOut visit_resident(const Rep &rp, const Rates *__restrict__ rt, 
                 rej = (uint32_t)mm < thr;
             }
         }
-        const double x = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x;
+        // x + 1/2, as in visit_domain
+        const double xh = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x + 0.5;
         uint64_t left = __ballot(valid);
         double Rb = 0.0;
         int pos = 0;
-        uint64_t cand = __ballot(x < R) & left;
+        uint64_t cand = __ballot(xh < R) & left;
         while (cand) {
             const int e = __builtin_ctzll(cand);
             left &= ~1ull << e;
             m_null += (uint32_t)(e - pos);
-            const double xe = rdl_f64(x, e);
+            const double xe = rdl_f64(xh, e);
             if (lane == e) Rb = R;
 
             // rate class and member index (exact, as in visit_domain)
             const int c = __builtin_ctzll(__ballot(xe < Pinc));
-            const double q = ((xe + 0.5) - (Pinc - W)) * inv_lane;
+            const double q = (xe - (Pinc - W)) * inv_lane;
             const uint32_t j = (uint32_t)rdl_f64(q, c);
 
             if constexpr (SCORE) {
@@ -219,7 +220,7 @@ __device__ VisitOut visit_resident(const Rep &rp, const Rates *__restrict__ rt, 
             Pinc = scan16_f64(W);
             R = rdl_f64(Pinc, 9);
             pos = e + 1;
-            cand = __ballot(x < R) & left;
+            cand = __ballot(xh < R) & left;
         }
         m_null += (uint32_t)__popcll(left);
         if (Rb != 0.0) {

@@ -10,8 +10,10 @@ one-domain-per-wavefront), and must match the oracle bit for bit:
   that dominates the coupling;
 * N_I = 1 (one tick per visit) and N_I far above the domain size and not a
   multiple of the 64-tick batch;
-* the smallest checkerboard (2 x 2 domains of 4 x 4), 64 x 64 domains
-  (64-bit rows), and a 12 x 12 domain (the slot draw rejects 2^32 mod 144);
+* the smallest checkerboard (2 x 2 domains of 4 x 4), 32 x 32 and 64 x 64
+  domains (rows that fill a 32-bit or a 64-bit mask, so the last column is
+  a neighbour of the next to last), and a 12 x 12 domain (the slot draw
+  rejects 2^32 mod 144);
 * calls with no sweeps and calls with no record point.
 """
 import numpy as np
@@ -41,6 +43,7 @@ CASES = {
     "long_visit": dict(L=16, tile=8, T=2.3, steps_per_visit=1000),
     "smallest": dict(L=8, tile=4, T=2.0),
     "tile64": dict(L=128, tile=64, T=2.6, h=-0.05),
+    "tile32": dict(L=64, tile=32, T=2.4, h=0.05),
     "odd_domain": dict(L=48, tile=12, T=2.2, h=0.1),
 }
 FORMS = {"phased": 0,
