@@ -42,12 +42,12 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
-    "kernel_source_sha256": "8ffb538ab8c167a6b7c3e87387045cc039b828cf11181ce178fd1159b0754c1e",
+    "kernel_source_sha256": "5b543c1626e0571f253c94641f56c23ebab43f96ffb6604bdc87e71d38f77a49",
     "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
     # k_flow: per sweep (the counter runs launch 40 sweeps per dispatch);
     # k_phase: per launch (one colour phase)
-    "kib": {"k_flow<uint32_t,false,false>": (3410.48, 1218.91),
-            "k_phase<uint32_t,false,false>": (947.01, 288.0)},
+    "kib": {"k_flow<uint32_t,false,false>": (3399.58, 1218.89),
+            "k_phase<uint32_t,false,false>": (944.01, 288.0)},
 }
 # algorithmic bytes per colour phase of the plain workload: each of the 256
 # domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the

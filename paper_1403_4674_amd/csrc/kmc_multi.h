@@ -285,10 +285,10 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // this lane's neighbours of the flipped site (nm, as in
             // visit_domain): read at xa and xb, kept where nm has the bit
             const bool on_row = sl == ys;
-            const bool adj = (sl == ys - 1 || sl == ys + 1) && sl < B;
+            const bool near = (uint32_t)(sl - ys + 1) <= 2u && sl < B;  // rows ys - 1 .. ys + 1
             const uint32_t bx = 1u << xs;
             const uint32_t mrow = ((bx << 1) | (bx >> 1)) & vm_row;
-            const uint32_t nm = on_row ? mrow : (adj ? bx : 0u);
+            const uint32_t nm = near ? (on_row ? mrow : bx) : 0u;
             const int xa = (xs - (on_row ? 1 : 0)) & 31, xb = (xs + 1) & 31;
             const uint32_t va = (nm >> xa) & 1u, vb = (nm >> xb) & 1u;
             uint32_t nb = (va << class_pos3<uint32_t>(S, P, xa)) +
