@@ -12,8 +12,9 @@ its neighbours that precede it in the schedule are done; KMC_F_FLOW).
 Extra measurements on the same line: the same workload as four phase
 launches per sweep, the batched persistent form (4096 ragged replicas), the
 backward score replay and fused score (1024 replicas of 64x64), the
-roofline of the dominant kernel and the serial CPU oracle on a bounded
-sample of the same workload.
+roofline of the dominant kernel, the serial CPU oracle on a bounded sample
+of the same workload (one core), and the oracle on the batch with one
+process per host core.
 """
 import argparse
 import json
@@ -197,6 +198,50 @@ def cpu_baseline(budget_s):
                        f"{sec:.1f} s")
 
 
+def _cpu_batched_worker(job):
+    """One host process of cpu_batched: its share of the batch (every n-th
+    replica), one sweep of each in turn, until the budget is used."""
+    wid, n_workers, budget_s = job
+    from oracle import kmco
+    from paper_1403_4674_amd import workloads
+    seed, descs, _ = workloads.batched_4096()
+    mine = []
+    for rho in range(wid, len(descs), n_workers):
+        d = descs[rho]
+        mine.append((kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
+                                  steps_per_visit=d["steps_per_visit"], seed=seed,
+                                  replica=rho), d["L"] ** 2))
+    ticks, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        for o, per_sweep in mine:
+            o.run(1, 1)
+            ticks += per_sweep
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    return ticks, time.perf_counter() - t0
+
+
+def cpu_batched(budget_s, cores=None):
+    """The serial oracle, as it stands, on the batched workload: one process
+    per host core (at most 16), each sweeping its share of the 4096 replicas
+    one sweep at a time for about budget_s seconds.  Aggregate
+    site-updates/s over all processes."""
+    import multiprocessing as mp
+    from oracle import build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    n = cores or min(16, len(os.sched_getaffinity(0)))
+    # spawned children start fresh interpreters that never touch the GPU
+    with mp.get_context("spawn").Pool(n) as pool:
+        res = pool.map(_cpu_batched_worker, [(w, n, budget_s) for w in range(n)])
+    ticks = sum(r[0] for r in res)
+    sec = max(r[1] for r in res)
+    return dict(value=ticks / sec, unit="site-updates/s", cores=n, kind="oracle",
+                sample=f"{n} processes, each sweeping every {n}-th replica of the 4096-replica "
+                       f"batch (one sweep per replica in turn), serial C oracle, "
+                       f"{sec:.1f} s")
+
+
 def copy_probe(nbytes):
     """A plain device copy of known size (PMC byte-counter calibration)."""
     import torch
@@ -340,6 +385,8 @@ def main():
                             / line.get("plain_phased", {"value": value})["value"]}
         line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["cpu_batched"] = cpu_batched(args.cpu_seconds * 2 / 3)
+        line["batched"]["vs_cpu_batched"] = line["batched"]["value"] / line["cpu_batched"]["value"]
     print(json.dumps(line), flush=True)
 
 
