@@ -383,6 +383,19 @@ def main():
                             "fused_vs_plain": (g["ticks"] / g["fused"]) / value,
                             "fused_vs_plain_phased": (g["ticks"] / g["fused"])
                             / line.get("plain_phased", {"value": value})["value"]}
+        # the same comparison counted in replicas advanced by one sweep per
+        # second (the plain workload is one replica of 1024^2); site-updates/s
+        # above is the stricter unit, as the batches hold smaller replicas
+        plain_rs = value / (1024 * 1024)
+        line["replica_sweeps_per_s"] = {
+            "plain": plain_rs,
+            "batched": b["replicas"] * b["sweeps"] / b["sec"],
+            "fused_score": g["replicas"] * g["sweeps"] / g["fused"],
+        }
+        line["replica_sweeps_per_s"]["batched_vs_plain"] = (
+            line["replica_sweeps_per_s"]["batched"] / plain_rs)
+        line["replica_sweeps_per_s"]["fused_score_vs_plain"] = (
+            line["replica_sweeps_per_s"]["fused_score"] / plain_rs)
         line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         line["cpu_batched"] = cpu_batched(args.cpu_seconds * 2 / 3)
