@@ -43,11 +43,11 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
-    "kernel_source_sha256": "5b543c1626e0571f253c94641f56c23ebab43f96ffb6604bdc87e71d38f77a49",
+    "kernel_source_sha256": "f5db0cc9d99097e47b0bf68892a3b431812dea6a970fbd76ae8cdc705cf0aabe",
     "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
     # k_flow: per sweep (the counter runs launch 40 sweeps per dispatch);
     # k_phase: per launch (one colour phase)
-    "kib": {"k_flow<uint32_t,false,false>": (3399.58, 1218.89),
+    "kib": {"k_flow<uint32_t,false,false>": (3399.85, 1218.99),
             "k_phase<uint32_t,false,false>": (944.01, 288.0)},
 }
 # algorithmic bytes per colour phase of the plain workload: each of the 256
