@@ -625,6 +625,19 @@ __device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
     planes_step_inv<MT>(P, m, inc ? (MT)0 : ~(MT)0);
 }
 
+// m / den for the score of a run of m null ticks (den > 0): the hardware
+// reciprocal refined by two Newton steps (within an ulp of 1/den), times m.
+// Cheaper than the correctly rounded quotient; every form of the score uses
+// it, so fused and replayed scores agree bit for bit.
+__device__ __forceinline__ double null_quot(uint32_t m, double den) {
+    double r = __builtin_amdgcn_rcp(den);
+    double e = __builtin_fma(-den, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-den, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return (double)m * r;
+}
+
 struct VisitOut {
     int64_t events;
     int64_t dM, dB;
@@ -754,7 +767,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         const double nl = (double)n_lane;
         const double Rw = rowsum16_f64(nl * w_lane, lane);
         const double den = (double)nd - Rw;
-        if (den > 0.0) A_lane += ((double)m / den) * nl;
+        if (den > 0.0) A_lane += null_quot(m, den) * nl;
     };
 
     for (int base = 0; base < NI; base += 64) {

@@ -213,7 +213,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
         const double nl = (double)n_lane;
         const double Rw = sum_row_f64(nl * w_lane, base);
         const double den = (double)nd - Rw;
-        if (act && m && den > 0.0) A_lane += ((double)m / den) * nl;
+        if (act && m && den > 0.0) A_lane += null_quot(m, den) * nl;
     };
 
     for (int b0 = 0; b0 < NI; b0 += kSlotW) {

@@ -107,7 +107,7 @@ __device__ VisitOut visit_resident(const Rep &rp, const Rates *__restrict__ rt, 
         const double nl = (double)n_lane;
         const double Rw = rowsum16_f64(nl * w_lane, lane);
         const double den = (double)nd - Rw;
-        if (den > 0.0) A_lane += ((double)m / den) * nl;
+        if (den > 0.0) A_lane += null_quot(m, den) * nl;
     };
 
     for (int base = 0; base < NI; base += 64) {
