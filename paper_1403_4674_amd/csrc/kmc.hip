@@ -382,7 +382,8 @@ void launch_flow(kmc_ctx *c, KParams K, int G) {
             });
         }
     });
-    hipLaunchKernelGGL(kmcdev::k_flow_close, dim3(c->n_rep), dim3(64), 0, c->stream, K, G);
+    hipLaunchKernelGGL(kmcdev::k_flow_close, dim3(c->n_rep), dim3(64 * kmcdev::kFlowCloseWaves),
+                       0, c->stream, K, G);
     hipLaunchKernelGGL(kmcdev::k_advance, dim3(1), dim3(1), 0, c->stream, K.ctl, (int64_t)G);
     launch_check(c, "flow launch");
 }

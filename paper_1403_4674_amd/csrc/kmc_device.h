@@ -1170,23 +1170,39 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
     }
 }
 
-// After a dataflow launch of G sweeps: one wavefront per replica adds the
-// sweeps' changes to the running totals in sweep order and writes the
-// records that fall due, with the replica time from the clock snapshots
-// (the same fixed-order mean as replica_time).
-__global__ __launch_bounds__(64) void k_flow_close(KParams K, int G) {
+// After a dataflow launch of G sweeps: one workgroup per replica.  Its first
+// thread adds the sweeps' changes to the running totals in sweep order; its
+// wavefronts then write the records that fall due, one sweep each at a
+// time, with the replica time from the clock snapshots (the same fixed-order
+// mean as replica_time).
+constexpr int kFlowCloseWaves = 16;
+
+__global__ __launch_bounds__(64 * kFlowCloseWaves) void k_flow_close(KParams K, int G) {
+    __shared__ int64_t tot[kFlowMaxSweeps][3];  // running totals after sweep g
     const int rho = blockIdx.x;
     const Ctl c = *K.ctl;
     const Rep rp = K.reps[rho];
     const int lane = __lane_id();
-    RepAcc acc = K.acc[rho];
-    for (int g = 0; g < G; ++g) {
-        const int64_t *a = K.flow_acc + ((int64_t)g * K.n_rep + rho) * 3;
-        acc.M += a[0];
-        acc.B += a[1];
-        acc.events += a[2];
+    const int wave = (int)(threadIdx.x >> 6);
+    if (threadIdx.x == 0) {
+        RepAcc acc = K.acc[rho];
+        for (int g = 0; g < G; ++g) {
+            const int64_t *a = K.flow_acc + ((int64_t)g * K.n_rep + rho) * 3;
+            acc.M += a[0];
+            acc.B += a[1];
+            acc.events += a[2];
+            tot[g][0] = acc.M;
+            tot[g][1] = acc.B;
+            tot[g][2] = acc.events;
+        }
+        K.acc[rho] = acc;
+    }
+    __syncthreads();
+    if (!K.write_records) return;
+    // the records due, one sweep per wavefront at a time
+    for (int g = wave; g < G; g += kFlowCloseWaves) {
         const int64_t done = c.run_done + g + 1;
-        if (!K.write_records || done % c.rec_every) continue;
+        if (done % c.rec_every) continue;
         double s = 0.0, cpen = 0.0;
         for (int dd = lane; dd < rp.ND; dd += 64) {
             const double *ck = K.flow_clk + ((int64_t)g * K.n_dom_total + rp.dom_off + dd) * 2;
@@ -1197,15 +1213,14 @@ __global__ __launch_bounds__(64) void k_flow_close(KParams K, int G) {
             const int64_t k = c.rec_base + done / c.rec_every - 1;
             Record r;
             r.sweep = c.sweep + g + 1;
-            r.M = acc.M;
-            r.B = acc.B;
-            r.events = acc.events;
+            r.M = tot[g][0];
+            r.B = tot[g][1];
+            r.events = tot[g][2];
             r.steps = (c.sweep + g + 1) * (int64_t)rp.NI * rp.ND * rp.visits;
             r.t = t;
             K.rec[k * K.n_rep + rho] = r;
         }
     }
-    if (lane == 0) K.acc[rho] = acc;
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
