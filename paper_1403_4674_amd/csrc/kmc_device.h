@@ -1146,6 +1146,12 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
         (uint32_t)vis, w, (uint32_t)rho, K.seed, dm, lds);
     if (__lane_id() == 0) {
+        // this domain's visits so far in sweep w (the palindrome's second
+        // visit has vis = 1), published first: the visits waiting on it need
+        // only the tile and the domain record, both written above
+        __hip_atomic_store(dn + d, base + (int64_t)vis + 1,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // what only k_flow_close reads, after the launch
         if (o.events) {
             int64_t *a = K.flow_acc + ((int64_t)g * K.n_rep + rho) * 3;
             atomicAdd((unsigned long long *)&a[0], (unsigned long long)o.dM);
@@ -1163,10 +1169,6 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
             atomicAdd(bb, o.sJ);
             atomicAdd(bb + 1, o.sh);
         }
-        // this domain's visits so far in sweep w (the palindrome's second
-        // visit has vis = 1)
-        __hip_atomic_store(dn + d, base + (int64_t)vis + 1,
-                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
