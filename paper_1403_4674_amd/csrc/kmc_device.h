@@ -273,6 +273,13 @@ __device__ __forceinline__ uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
 }
 
+// DPP move with bound control: lanes whose source is out of range read 0
+// (all rows and banks written, so no previous value is needed).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dppz(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
 // sched_barrier mask: scalar instructions may be moved across, vector ones not
 constexpr int kSchedScalarMayCross = 0x4;
 
@@ -295,10 +302,10 @@ __device__ __forceinline__ T dpp_any(T v) {
 
 // Inclusive prefix sum over the 64 lanes.
 __device__ __forceinline__ uint32_t scan64(uint32_t v) {
-    v += dpp<kRowShr + 1>(v);
-    v += dpp<kRowShr + 2>(v);
-    v += dpp<kRowShr + 4>(v);
-    v += dpp<kRowShr + 8>(v);
+    v += dppz<kRowShr + 1>(v);
+    v += dppz<kRowShr + 2>(v);
+    v += dppz<kRowShr + 4>(v);
+    v += dppz<kRowShr + 8>(v);
     v += dpp<kRowBcast15, 0xA>(v);
     v += dpp<kRowBcast31, 0xC>(v);
     return v;
@@ -330,13 +337,6 @@ __device__ __forceinline__ double rdl_f64(double v, int lane) {
     return __longlong_as_double((long long)rdl64((uint64_t)__double_as_longlong(v), lane));
 }
 
-// DPP move with bound control: lanes whose source is out of range read 0
-// (all rows and banks written, so no previous value is needed).
-template <int CTRL>
-__device__ __forceinline__ uint32_t dppz(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dppz_f64(double v) {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -356,10 +356,10 @@ __device__ __forceinline__ double scan16_f64(double v) {
 
 // Inclusive prefix sum over lanes 0..31 (lanes 32..63 get sums of their own).
 __device__ __forceinline__ uint32_t scan32(uint32_t v) {
-    v += dpp<kRowShr + 1>(v);
-    v += dpp<kRowShr + 2>(v);
-    v += dpp<kRowShr + 4>(v);
-    v += dpp<kRowShr + 8>(v);
+    v += dppz<kRowShr + 1>(v);
+    v += dppz<kRowShr + 2>(v);
+    v += dppz<kRowShr + 4>(v);
+    v += dppz<kRowShr + 8>(v);
     v += dpp<kRowBcast15, 0xA>(v);
     return v;
 }

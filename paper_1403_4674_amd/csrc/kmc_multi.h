@@ -48,11 +48,21 @@ __device__ __forceinline__ uint32_t seg16(uint64_t m, int slot) {
 }
 
 // Inclusive prefix sum inside each 16-lane row.
+// The vector conversion of a double to uint32 saturates (negative and NaN to
+// 0, too large to 2^32 - 1).  Lanes other than the class lane of a slot
+// convert values outside that range; written as the instruction itself so
+// that the conversion is defined for them (only lane c's value is read).
+__device__ __forceinline__ uint32_t cvt_u32_sat(double q) {
+    uint32_t r;
+    asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(q));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t scan_row(uint32_t v) {
-    v += dpp<kRowShr + 1>(v);
-    v += dpp<kRowShr + 2>(v);
-    v += dpp<kRowShr + 4>(v);
-    v += dpp<kRowShr + 8>(v);
+    v += dppz<kRowShr + 1>(v);
+    v += dppz<kRowShr + 2>(v);
+    v += dppz<kRowShr + 4>(v);
+    v += dppz<kRowShr + 8>(v);
     return v;
 }
 
@@ -256,7 +266,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             // shift below stays in range (its results are discarded)
             const int c = __builtin_ctz(cseg_c | 0x200u);
             const double q = (xe - (Pinc - W)) * inv_lane;
-            const uint32_t jl = (uint32_t)fmin(fmax(q, 0.0), 65535.0);
+            const uint32_t jl = cvt_u32_sat(q);
             const uint32_t j = sbc32(jl, base + c);
 
             if constexpr (SCORE) {
