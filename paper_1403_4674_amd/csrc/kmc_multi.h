@@ -199,6 +199,10 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     const double rd_lane = (A.on && sl < 10) ? rt->rd[sl] : 0.0;
     const double inv_lane = (A.on && sl < 10) ? rt->inv_rd[sl] : 0.0;
     const uint32_t sl3 = sl < 10 ? 3u * (uint32_t)sl : 30u;  // tally field (30: always 0)
+    // the fields a class lane's count moves from: the class above (the
+    // flipped spin was +1, its neighbours lose an up neighbour) or below
+    const uint32_t from_up = sl < 9 ? sl3 + 3u : 30u;
+    const uint32_t from_dn = sl >= 1 && sl < 10 ? sl3 - 3u : 30u;
     double W = (double)n_lane * rd_lane;
     double Pinc = scan16_f64(W);
     double R = rowbcast_f64<9>(Pinc);
@@ -288,8 +292,8 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
             const uint32_t xseg = seg16(__ballot(rank_incl > jr), slot);
             const int xs = __builtin_ctz(xseg | 0x10000u);
 
-            // packed class tallies of the flipped site and its in-tile
-            // neighbours, the three rows summed inside the slot by DPP
+            // packed class tallies of the flipped site's in-tile neighbours,
+            // the three rows summed inside the slot by DPP
             const bool up = c >= 5;
             const int c_new = up ? c - 5 : c + 5;
             // this lane's neighbours of the flipped site (nm, as in
@@ -305,11 +309,13 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
                           (vb << class_pos3<uint32_t>(S, P, xb));
             nb += dppz<kRowShr + 1>(nb) + dppz<kRowShl1>(nb);
             const uint32_t nb_s = sbc32(nb, base + ys);
-            const uint32_t sub_s = nb_s + (1u << (3 * c));
-            const uint32_t add_s =
-                (uint32_t)(((uint64_t)nb_s << 3) >> (up ? 6 : 0)) + (1u << (3 * c_new));
             if (act) {
-                n_lane = n_lane + ((add_s >> sl3) & 7u) - ((sub_s >> sl3) & 7u);
+                // every neighbour moves one class up (flip to +1) or down, so
+                // class lane l gains the neighbours of class l -/+ 1 and loses
+                // its own; the flipped site moves from c to c -/+ 5
+                n_lane = n_lane + __builtin_amdgcn_ubfe(nb_s, up ? from_up : from_dn, 3) -
+                         __builtin_amdgcn_ubfe(nb_s, sl3, 3) + (sl == c_new ? 1u : 0u) -
+                         (sl == c ? 1u : 0u);
                 ev_lane += sl == c ? 1u : 0u;
             }
             W = (double)n_lane * rd_lane;
@@ -554,10 +560,10 @@ __device__ void run_item(const KParams &K, const MItem &it, int wave, int lane, 
 // Multi-slot persistent kernel: workgroup items (teams of four wavefronts)
 // first, then wavefront items; every wavefront leaves once both queues are
 // drained.  Occupancy: the forward instantiation is held to 168 registers
-// (three wavefronts per SIMD, no spills); the score one to 128 (four per
-// SIMD: it spills a few bytes outside the event loop and runs ~9% faster
-// than at three on the differentiable batch, while the forward one at four
-// loses ~13% on the ragged batch).
+// (three wavefronts per SIMD), the score one to 128 (four per SIMD: it runs
+// ~9% faster than at three on the differentiable batch, while the forward
+// one at four loses ~13% on the ragged batch).  Both spill a few values of
+// the item and sweep loops, none inside the tick loop.
 template <bool SCORE>
 __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) __attribute__((amdgpu_waves_per_eu(SCORE ? 4 : 3, 8))) void k_persistent_multi(
     KParams K, const MItem *__restrict__ items, int n_wg_items, int n_wave_items,
