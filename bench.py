@@ -43,12 +43,12 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
 # kernel source the counters were taken on; reported as null otherwise.
 PLAIN_TRAFFIC = {
-    "kernel_source_sha256": "5b0d4bdf3d0966c5ff5c0b6b49ff632ef96e8d4a8c424b8eea85f870b55779b3",
+    "kernel_source_sha256": "ebae7473953b539bc3255dafa34b7fdd232a7132252188d1983b1111d503e395",
     "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
     # k_flow: per sweep (the counter runs launch 40 sweeps per dispatch);
     # k_phase: per launch (one colour phase)
-    "kib": {"k_flow<uint32_t,false,false>": (3400.22, 1218.93),
-            "k_phase<uint32_t,false,false>": (944.01, 288.0)},
+    "kib": {"k_flow<uint32_t,false,false>": (3400.95, 1218.22),
+            "k_phase<uint32_t,false,false>": (940.51, 288.0)},
 }
 # algorithmic bytes per colour phase of the plain workload: each of the 256
 # domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the
