@@ -246,6 +246,14 @@ kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out);
 kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *clk_sum,
                                 double *clk_comp, int64_t *events);
 
+/* The per-domain clocks alone (each domain advances its own clock by the
+ * residence times of its events, Eq. (Poisson Distribution); the replica
+ * time is their mean): t and comp receive N_D doubles each, the compensated
+ * clock sums and their compensation terms, as kmc_get_domain_state with no
+ * event counts; either may be NULL.  Errors as kmc_get_domain_state.
+ * Synchronises. */
+kmc_status kmc_get_domain_clocks(kmc_ctx *c, int32_t replica, double *t, double *comp);
+
 /* Number of replicas, and the number of domains of one replica. */
 kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
                         int32_t *n_domains);

@@ -1239,6 +1239,11 @@ extern "C" kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *
     return KMC_OK;
 }
 
+extern "C" kmc_status kmc_get_domain_clocks(kmc_ctx *c, int32_t replica, double *t,
+                                            double *comp) {
+    return kmc_get_domain_state(c, replica, t, comp, nullptr);
+}
+
 extern "C" kmc_status kmc_get_info(kmc_ctx *c, int32_t replica, int32_t *n_rep,
                                    int32_t *n_domains) {
     if (!c) return KMC_EINVAL;

@@ -71,6 +71,7 @@ def lib():
             "kmc_backward_score": ([P, P, I64, C.c_uint32], I32),
             "kmc_get_spins": ([P, I32, P], I32),
             "kmc_get_domain_state": ([P, I32, P, P, P], I32),
+            "kmc_get_domain_clocks": ([P, I32, P, P], I32),
             "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
             "kmc_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], I32),
             "kmc_exact_sweeps": ([C.POINTER(ReplicaDesc), P, P, I64, C.c_uint32, P], I32),
@@ -91,7 +92,8 @@ def exported_symbols():
     L = lib()
     names = ["kmc_set_device_allocator", "kmc_rate_table", "kmc_init_lattice",
              "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
-             "kmc_get_domain_state", "kmc_get_info", "kmc_get_timing", "kmc_last_error",
+             "kmc_get_domain_state", "kmc_get_domain_clocks", "kmc_get_info",
+             "kmc_get_timing", "kmc_last_error",
              "kmc_destroy", "kmc_exact_sweeps", "kmc_set_wait_limit"]
     return [n for n in names if hasattr(L, n)]
 
@@ -239,6 +241,14 @@ def kmc_get_domain_state(ctx, replica):
     return s, c, e
 
 
+def kmc_get_domain_clocks(ctx, replica):
+    nd = C.c_int32(0)
+    _check(lib().kmc_get_info(ctx, replica, None, C.byref(nd)), ctx)
+    t, c = np.zeros(nd.value), np.zeros(nd.value)
+    _check(lib().kmc_get_domain_clocks(ctx, replica, _ptr(t), _ptr(c)), ctx)
+    return t, c
+
+
 def kmc_get_timing(ctx):
     """(milliseconds, launches) of the hot-kernel launches timed since the
     last call (runs with F_TIMING)."""
@@ -274,6 +284,9 @@ class Lattice:
 
     def domain_state(self, replica=0):
         return kmc_get_domain_state(self.ctx, replica)
+
+    def domain_clocks(self, replica=0):
+        return kmc_get_domain_clocks(self.ctx, replica)
 
     def set_wait_limit(self, max_polls):
         """Bound of each dataflow wait (a hook for testing the failure path)."""

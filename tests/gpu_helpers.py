@@ -34,6 +34,8 @@ def assert_replica_equal(lat, rho, ora, gpu_rec=None, ora_rec=None, what=""):
     diff = np.argwhere(g != o)
     assert diff.size == 0, (what, "spins differ at", diff[:5])
     s, c, e = lat.domain_state(rho)
+    t, tc = lat.domain_clocks(rho)  # the clocks-only call returns the same
+    assert np.array_equal(t, s) and np.array_equal(tc, c), (what, "domain clocks")
     os_, oc = ora.domain_clocks()
     assert np.array_equal(e, ora.domain_events()), (what, "domain events")
     np.testing.assert_allclose(s + c, os_ + oc, rtol=RTOL_T, atol=0, err_msg=what)

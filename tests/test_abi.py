@@ -94,6 +94,8 @@ def test_calls_reject_null_context(kmc):
     assert L.kmc_backward_score(None, None, 0, 0) == kmc.KMC_EINVAL
     assert L.kmc_get_spins(None, 0, None) == kmc.KMC_EINVAL
     assert L.kmc_set_wait_limit(None, 5) == kmc.KMC_EINVAL
+    assert L.kmc_get_domain_clocks(None, 0, None, None) == kmc.KMC_EINVAL
+    assert L.kmc_get_domain_state(None, 0, None, None, None) == kmc.KMC_EINVAL
     assert L.kmc_last_error(None) == b"null context"
 
 
