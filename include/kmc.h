@@ -53,9 +53,11 @@ typedef enum {
     KMC_EUNSUPPORTED = -5   /* valid for the method, not for this library   */
 } kmc_status;
 
-enum { KMC_RATE_METROPOLIS = 0, KMC_RATE_BARKER = 1 };
-enum { KMC_SCHED_RANDOM_PERM = 0, KMC_SCHED_PALINDROME = 1 };
-enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 };
+/* values of the descriptor fields rate_model, schedule and init (held there
+ * as int32_t) */
+typedef enum { KMC_RATE_METROPOLIS = 0, KMC_RATE_BARKER = 1 } kmc_rate_model;
+typedef enum { KMC_SCHED_RANDOM_PERM = 0, KMC_SCHED_PALINDROME = 1 } kmc_schedule;
+typedef enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 } kmc_init;
 
 /* flags of kmc_run_schedule */
 #define KMC_F_CHECKPOINT 0x1u  /* save the start state for kmc_backward_score */

@@ -121,3 +121,29 @@ def test_allocator_hooks_must_come_in_pairs(kmc):
     assert L.kmc_set_device_allocator(alloc, C.cast(None, kmc._FREE_FN), None) == kmc.KMC_EINVAL
     assert L.kmc_set_device_allocator(C.cast(None, kmc._ALLOC_FN),
                                       C.cast(None, kmc._FREE_FN), None) == kmc.KMC_OK
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    """include/kmc.h is a C header: plain C11 with no HIP or torch types."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "kmc.h"\n'
+        "int main(void) {\n"
+        "    kmc_rate_model m = KMC_RATE_BARKER;\n"
+        "    kmc_schedule s = KMC_SCHED_PALINDROME;\n"
+        "    kmc_init i = KMC_INIT_ALL_UP;\n"
+        "    kmc_replica_desc d = {0};\n"
+        "    kmc_record r = {0};\n"
+        "    kmc_status (*f)(kmc_ctx *, int32_t, double *, double *) = kmc_get_domain_clocks;\n"
+        "    (void)d; (void)r; (void)f;\n"
+        "    return (int)m + (int)s + (int)i - 3;\n"
+        "}\n")
+    exe = tmp_path / "use"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-c", "-I",
+                    os.path.join(ROOT, "include"), str(src), "-o", str(exe) + ".o"],
+                   check=True)
+
