@@ -213,16 +213,23 @@ kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t record_every,
 /* All execution forms give bit-identical results; KMC_F_MULTI and
  * KMC_F_NO_MULTI only change how the work is laid out on the GPU. */
 
-/* Copies all records so far: out[rep * capacity + k] for replica rep and
- * record k < min(capacity, *n_rec_out).  *n_rec_out receives the number of
- * records per replica.  out may be NULL to query the count.  Host output
- * synchronises the stream; with KMC_F_DEVICE_OUT out is device memory and
- * the copy is only enqueued. */
+/* Endpoint statistics (Sec. 2.3: samples are valid only at the end of
+ * domain processes, here the ends of whole sweeps; the paper's ensemble
+ * averages, Eq. (time dependent averages), are formed from them over
+ * replicas).  Copies all records so far: out[rep * capacity + k] for replica
+ * rep and record k < min(capacity, *n_rec_out).  *n_rec_out receives the
+ * number of records per replica.  out may be NULL to query the count.  Host
+ * output synchronises the stream and returns KMC_EDEVICE when a dataflow
+ * wait of an earlier run gave up (the results are void); with
+ * KMC_F_DEVICE_OUT out is device memory and the copy is only enqueued. */
 kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capacity,
                            int64_t *n_rec_out, uint32_t flags);
 
 /* Likelihood-ratio path score of the last kmc_run_schedule call made with
- * KMC_F_CHECKPOINT or KMC_F_SCORE.  With KMC_F_SCORE the run accumulated the
+ * KMC_F_CHECKPOINT or KMC_F_SCORE.  This extends the paper, which has no
+ * derivatives: it is d ln P(path)/d(J, h) of the tick chain the paper
+ * defines (Sec. 2.2, App. A Eq. (Glauber_TM)), whose average against an
+ * observable gives the gradient of that observable's expectation.  With KMC_F_SCORE the run accumulated the
  * score itself and this call copies it out.  Otherwise the call replays the
  * run from its saved start state with a dedicated kernel (bit-exact: every
  * decision is integer) and accumulates, for every tick, d ln P/d(J, h) of the
@@ -238,13 +245,13 @@ kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capacity,
                               uint32_t flags);
 
 /* Copies replica `replica`'s lattice (L*L int8, row-major) to host memory.
- * Synchronises. */
+ * Synchronises; KMC_EDEVICE when a dataflow wait of an earlier run gave up. */
 kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out);
 
 /* Copies the per-domain clock sums and their compensation terms (N_D
  * doubles each, domain d = ty*(L/B) + tx) and per-domain event counts
  * (N_D int64) of one replica to host memory; any pointer may be NULL.
- * Synchronises. */
+ * Synchronises; KMC_EDEVICE when a dataflow wait of an earlier run gave up. */
 kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *clk_sum,
                                 double *clk_comp, int64_t *events);
 

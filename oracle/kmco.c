@@ -230,6 +230,8 @@ struct kmco_state {
     uint64_t *bits;        /* [10][nw]                                    */
     int8_t *cls;           /* [nd]                                        */
     int64_t check_fail;
+    int64_t retry_ticks;   /* ticks whose slot needed at least one redraw */
+    int64_t retry_draws;   /* redraws on the retry streams, in total      */
 };
 
 static inline int wrap(int a, int L) { a %= L; return a < 0 ? a + L : a; }
@@ -388,6 +390,28 @@ static void null_score(const kmco_state *s, const int64_t n[10], double nu[2])
     }
 }
 
+/* Magnitude of the same null term before cancellation:
+ * sum_c n_c |w_c g_c| / (n_d - R_w) per theta, the sum of the absolute values
+ * of the per-class terms that make up nu_theta. */
+static void null_abs(const kmco_state *s, const int64_t n[10], double mag[2])
+{
+    double Rw = 0.0, AJ = 0.0, Ah = 0.0;
+    for (int c = 0; c < 10; ++c) {
+        double nc = (double)n[c];
+        Rw += nc * s->w[c];
+        AJ += nc * fabs(s->w[c] * s->gJ[c]);
+        Ah += nc * fabs(s->w[c] * s->gh[c]);
+    }
+    double den = (double)s->nd - Rw;
+    if (den > 0.0) {
+        mag[0] = AJ / den;
+        mag[1] = Ah / den;
+    } else {
+        mag[0] = 0.0;
+        mag[1] = 0.0;
+    }
+}
+
 static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
 {
     int64_t cnt[10] = {0};
@@ -406,7 +430,7 @@ static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
  * domain held fixed (the halo is read from the lattice, which no other
  * domain changes during the visit). */
 static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
-                         int flags, double *score)
+                         int flags, double *score, double *score_abs)
 {
     const int Bx = s->Bx, By = s->By, L = s->L;
     const int oy = (d / s->NTx) * By, ox = (d % s->NTx) * Bx;
@@ -424,8 +448,13 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         draw(s->seed, (uint32_t)t,
              (uint32_t)d | ((uint32_t)visit << 20) | (STREAM_TICK << 24),
              (uint32_t)w, (uint32_t)s->replica, o);
+        int32_t redraws = 0;
         uint32_t slot = kmco_tick_slot(s->seed, s->replica, w, d, visit,
-                                       (uint32_t)t, (uint32_t)s->nd, NULL);
+                                       (uint32_t)t, (uint32_t)s->nd, &redraws);
+        if (redraws) {
+            s->retry_ticks++;
+            s->retry_draws += redraws;
+        }
         uint64_t x = ((uint64_t)slot << 32) | o[0];
         if (x >= R) { /* null tick: the selected site is not flipped */
             ++m_null;
@@ -449,9 +478,19 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
                 null_score(s, n, nu);
                 score[0] += (double)m_null * nu[0];
                 score[1] += (double)m_null * nu[1];
+                if (score_abs) {
+                    double mag[2];
+                    null_abs(s, n, mag);
+                    score_abs[0] += (double)m_null * mag[0];
+                    score_abs[1] += (double)m_null * mag[1];
+                }
             }
             score[0] += s->gJ[c];
             score[1] += s->gh[c];
+            if (score_abs) {
+                score_abs[0] += fabs(s->gJ[c]);
+                score_abs[1] += fabs(s->gh[c]);
+            }
         }
         m_null = 0;
 
@@ -486,6 +525,12 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         null_score(s, n, nu);
         score[0] += (double)m_null * nu[0];
         score[1] += (double)m_null * nu[1];
+        if (score_abs) {
+            double mag[2];
+            null_abs(s, n, mag);
+            score_abs[0] += (double)m_null * mag[0];
+            score_abs[1] += (double)m_null * mag[1];
+        }
     }
     s->steps += s->NI;
 }
@@ -511,13 +556,13 @@ static void observe(const kmco_state *s, kmco_record *r)
 
 int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
                  int32_t flags, kmco_record *rec, int64_t rec_cap,
-                 double *score)
+                 double *score, double *score_abs)
 {
     if (!s || n_sweeps < 0 || record_every < 1) return -1;
     if ((flags & KMCO_F_SCORE) && !score) return -1;
     const int nc = s->ncol;
     int64_t nrec = 0;
-    double dummy[2];
+    double dummy[2], dummy_abs[2];
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const int64_t w = s->sweep;
         int order[18], visit[18], nphase;
@@ -543,10 +588,13 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
         double *sc = (flags & KMCO_F_SCORE)
                          ? (nrec < rec_cap ? score + 2 * nrec : dummy)
                          : NULL;
+        double *sa = (flags & KMCO_F_SCORE) && score_abs
+                         ? (nrec < rec_cap ? score_abs + 2 * nrec : dummy_abs)
+                         : NULL;
         for (int p = 0; p < nphase; ++p) {
             for (int d = 0; d < s->ND; ++d)
                 if (s->colour[d] == order[p])
-                    visit_domain(s, d, visit[p], w, flags, sc);
+                    visit_domain(s, d, visit[p], w, flags, sc, sa);
         }
         s->sweep++;
         if ((i + 1) % record_every == 0) {
@@ -580,6 +628,27 @@ int kmco_get_domain_events(const kmco_state *s, int64_t *events)
 }
 
 int64_t kmco_check_failures(const kmco_state *s) { return s ? s->check_fail : -1; }
+
+int kmco_get_retries(const kmco_state *s, int64_t *ticks, int64_t *draws)
+{
+    if (!s) return -1;
+    if (ticks) *ticks = s->retry_ticks;
+    if (draws) *draws = s->retry_draws;
+    return 0;
+}
+
+int64_t kmco_count_retry_ticks(uint64_t seed, int32_t replica, int64_t sweep,
+                               int32_t domain, int32_t visit, uint32_t n_ticks,
+                               uint32_t n)
+{
+    int64_t k = 0;
+    for (uint32_t t = 0; t < n_ticks; ++t) {
+        int32_t r = 0;
+        (void)kmco_tick_slot(seed, replica, sweep, domain, visit, t, n, &r);
+        k += r > 0;
+    }
+    return k;
+}
 
 int kmco_get_partition(const kmco_state *s, int32_t *colour, int32_t *n_colours)
 {

@@ -93,15 +93,30 @@ kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
 /* Runs n_sweeps sweeps.  After the i-th sweep of this call (1-based) a record
  * is written when i % record_every == 0.  With KMCO_F_SCORE the likelihood-
  * ratio score (d/dJ, d/dh) of every tick is added to score[2*k], score[2*k+1]
- * where k is the record that closes the interval holding the tick.
+ * where k is the record that closes the interval holding the tick; when
+ * score_abs is not NULL it receives, in the same layout, the sum of the
+ * absolute values of the terms making up that score (|d ln w_c/d theta| per
+ * event; per run of m null ticks m sum_c n_c |w_c d ln w_c/d theta| /
+ * (n_d - R_w)), the scale against which rounding differences of the score
+ * are judged.
  * Returns the number of records written, or a negative error code. */
 int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
                  int32_t flags, kmco_record *rec, int64_t rec_cap,
-                 double *score);
+                 double *score, double *score_abs);
 int kmco_get_spins(const kmco_state *s, int8_t *out);
 int kmco_get_domain_clocks(const kmco_state *s, double *sum, double *comp);
 int kmco_get_domain_events(const kmco_state *s, int64_t *events);
 int64_t kmco_check_failures(const kmco_state *s);
+/* Ticks of all runs so far whose slot was rejected at least once by the
+ * exact 1/n_d selection (Lemire rejection, App. A Eq. (Glauber_TM)) and
+ * redrawn on the retry streams, and the number of redraws. */
+int kmco_get_retries(const kmco_state *s, int64_t *ticks, int64_t *draws);
+/* Ticks t < n_ticks of one visit (seed, replica, sweep, domain, visit) whose
+ * slot in [0, n) needs a redraw.  Depends only on the counters and n, not on
+ * any lattice. */
+int64_t kmco_count_retry_ticks(uint64_t seed, int32_t replica, int64_t sweep,
+                               int32_t domain, int32_t visit, uint32_t n_ticks,
+                               uint32_t n);
 void kmco_destroy(kmco_state *s);
 
 #ifdef __cplusplus

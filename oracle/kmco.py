@@ -57,13 +57,17 @@ def lib():
         L.kmco_tick_slot.restype = C.c_uint32
         L.kmco_create.argtypes = [C.POINTER(Desc), C.c_uint64, C.c_int32, P]
         L.kmco_create.restype = P
-        L.kmco_run.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P]
+        L.kmco_run.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P, P]
         L.kmco_run.restype = C.c_int64
         L.kmco_get_spins.argtypes = [P, P]
         L.kmco_get_domain_clocks.argtypes = [P, P, P]
         L.kmco_get_domain_events.argtypes = [P, P]
         L.kmco_check_failures.argtypes = [P]
         L.kmco_check_failures.restype = C.c_int64
+        L.kmco_get_retries.argtypes = [P, P, P]
+        L.kmco_count_retry_ticks.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32,
+                                             C.c_int32, C.c_uint32, C.c_uint32]
+        L.kmco_count_retry_ticks.restype = C.c_int64
         L.kmco_destroy.argtypes = [P]
         _lib = L
     return _lib
@@ -109,6 +113,11 @@ def perm_from_index_n(idx, n):
     return p
 
 
+def count_retry_ticks(seed, replica, sweep, domain, visit, n_ticks, n):
+    """Ticks t < n_ticks of one visit whose slot in [0, n) is redrawn."""
+    return lib().kmco_count_retry_ticks(seed, replica, sweep, domain, visit, n_ticks, n)
+
+
 def tick_slot(seed, replica, sweep, domain, visit, tick, n):
     r = C.c_int32(0)
     v = lib().kmco_tick_slot(seed, replica, sweep, domain, visit, tick, n,
@@ -137,18 +146,30 @@ class Replica:
         if not self._h:
             raise ValueError("oracle rejected the replica description")
 
-    def run(self, n_sweeps, record_every=1, score=False, check=False):
+    def run(self, n_sweeps, record_every=1, score=False, check=False, score_abs=False):
+        """Records of n_sweeps sweeps; with score, also the score bins
+        [n_bins, 2]; with score_abs as well, the bins' sums of absolute
+        terms (the scale of rounding differences)."""
         cap = -(-n_sweeps // record_every) if n_sweeps else 0
         rec = np.zeros(max(cap, 1), RECORD_DTYPE)
         sc = np.zeros((max(cap, 1), 2))
-        flags = (F_SCORE if score else 0) | (F_CHECK if check else 0)
+        sa = np.zeros((max(cap, 1), 2))
+        flags = (F_SCORE if (score or score_abs) else 0) | (F_CHECK if check else 0)
         n = lib().kmco_run(self._h, n_sweeps, record_every, flags, _ptr(rec), cap,
-                           _ptr(sc))
+                           _ptr(sc), _ptr(sa) if score_abs else None)
         if n < 0:
             raise ValueError("oracle run failed")
+        if score_abs:
+            return rec[:n], sc[:cap], sa[:cap]
         if score:
             return rec[:n], sc[:cap]
         return rec[:n]
+
+    def retries(self):
+        """(ticks whose slot was redrawn, redraws) over all runs so far."""
+        t, d = C.c_int64(0), C.c_int64(0)
+        lib().kmco_get_retries(self._h, C.byref(t), C.byref(d))
+        return t.value, d.value
 
     def spins(self):
         out = np.zeros((self.L, self.L), np.int8)

@@ -356,6 +356,23 @@ void with_wrap(const kmc_ctx *c, int g, F f) {
 template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K);
 
+// A launch of 64-lane blocks covers fewer than 2^32 work-items (the grid
+// size of a dispatch is a 32-bit count of work-items).
+constexpr int64_t kMaxBlocks = ((int64_t)1 << 32) / 64 - 1;
+
+// Sweeps one dataflow launch may hold: kFlowMaxSweeps, fewer when the grid
+// of G sweeps x phases x tasks would not fit one dispatch (0: not even one).
+int flow_window(const kmc_ctx *c) {
+    const int64_t per_sweep = (int64_t)c->n_phase * std::max(c->n_tasks32, c->n_tasks - c->n_tasks32);
+    return (int)std::min<int64_t>(kmcdev::kFlowMaxSweeps, kMaxBlocks / std::max<int64_t>(per_sweep, 1));
+}
+
+unsigned flow_blocks(kmc_ctx *c, int G, int n_tasks) {
+    const int64_t b = (int64_t)G * c->n_phase * n_tasks;
+    if (b > kMaxBlocks) fail(c, KMC_EUNSUPPORTED, "dataflow grid too large");
+    return (unsigned)b;
+}
+
 // G sweeps (G <= kFlowMaxSweeps) as one dataflow launch per row-mask width
 // (replicas of the two widths never interact), then the records.
 template <bool SCORE>
@@ -368,18 +385,20 @@ void launch_flow(kmc_ctx *c, KParams K, int G) {
             K.task_begin = 0;
             with_wrap(c, 0, [&](auto W) {
                 hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value>),
-                                   dim3(G * c->n_phase * c->n_tasks32), dim3(64), 0,
+                                   dim3(flow_blocks(c, G, c->n_tasks32)), dim3(64), 0,
                                    c->stream, K, c->n_tasks32, c->n_phase, c->d_done);
             });
+            launch_check(c, "flow launch");
         }
         if (c->n_tasks > c->n_tasks32) {
             const int nt = c->n_tasks - c->n_tasks32;
             K.task_begin = c->n_tasks32;
             with_wrap(c, 1, [&](auto W) {
                 hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value>),
-                                   dim3(G * c->n_phase * nt), dim3(64), 0, c->stream, K, nt,
+                                   dim3(flow_blocks(c, G, nt)), dim3(64), 0, c->stream, K, nt,
                                    c->n_phase, c->d_done);
             });
+            launch_check(c, "flow launch");
         }
     });
     hipLaunchKernelGGL(kmcdev::k_flow_close, dim3(c->n_rep), dim3(64 * kmcdev::kFlowCloseWaves),
@@ -393,8 +412,9 @@ void launch_flow(kmc_ctx *c, KParams K, int G) {
 template <bool SCORE>
 void run_sweeps(kmc_ctx *c, KParams K, int64_t n) {
     if (c->flow) {
-        for (int64_t i = 0; i < n; i += kmcdev::kFlowMaxSweeps)
-            launch_flow<SCORE>(c, K, (int)std::min<int64_t>(kmcdev::kFlowMaxSweeps, n - i));
+        const int G = flow_window(c);
+        for (int64_t i = 0; i < n; i += G)
+            launch_flow<SCORE>(c, K, (int)std::min<int64_t>(G, n - i));
         return;
     }
     for (int64_t i = 0; i < n; ++i) launch_sweep<SCORE>(c, K);
@@ -1011,6 +1031,15 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
                          "replica " + std::to_string(rho) +
                              ": domains over 64 sites a side run only with KMC_F_RESIDENT");
         }
+        if (!(flags & (KMC_F_PERSISTENT | KMC_F_RESIDENT))) {
+            // one block per phase task: the phase launches need the task
+            // count below the dispatch limit, the dataflow launches one
+            // sweep of tasks per phase
+            if (c->n_tasks > kMaxBlocks)
+                fail(c, KMC_EUNSUPPORTED, "more phase tasks than one launch can hold");
+            if ((flags & KMC_F_FLOW) && flow_window(c) < 1)
+                fail(c, KMC_EUNSUPPORTED, "one dataflow sweep exceeds the launch grid limit");
+        }
         if (n_sweeps == 0) return KMC_OK;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
@@ -1134,8 +1163,10 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
                                           (size_t)n_bins * 2 * sizeof(double), c->n_rep, kind,
                                           c->stream),
                       "score copy");
-            if (!(flags & KMC_F_DEVICE_OUT))
+            if (!(flags & KMC_F_DEVICE_OUT)) {
                 hip_check(c, hipStreamSynchronize(c->stream), "score sync");
+                check_flow_error(c, c->d_ctl);
+            }
             return KMC_OK;
         }
         if (!c->have_ckpt)
@@ -1210,6 +1241,7 @@ extern "C" kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out) {
         hip_check(c, hipMemcpyAsync(out, c->d_spins + rp.spin_off, (size_t)rp.L * rp.L,
                                     hipMemcpyDeviceToHost, c->stream), "spin copy");
         hip_check(c, hipStreamSynchronize(c->stream), "spin sync");
+        check_flow_error(c, c->d_ctl);
     } catch (const Fail &f) {
         return f.st;
     }
@@ -1228,6 +1260,7 @@ extern "C" kmc_status kmc_get_domain_state(kmc_ctx *c, int32_t replica, double *
         hip_check(c, hipMemcpyAsync(h.data(), c->d_dom + rp.dom_off, sizeof(Dom) * rp.ND,
                                     hipMemcpyDeviceToHost, c->stream), "domain copy");
         hip_check(c, hipStreamSynchronize(c->stream), "domain sync");
+        check_flow_error(c, c->d_ctl);
         for (int i = 0; i < rp.ND; ++i) {
             if (clk_sum) clk_sum[i] = h[i].clk_sum;
             if (clk_comp) clk_comp[i] = h[i].clk_comp;

@@ -627,8 +627,11 @@ __device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
 
 // m / den for the score of a run of m null ticks (den > 0): the hardware
 // reciprocal refined by two Newton steps (within an ulp of 1/den), times m.
-// Cheaper than the correctly rounded quotient; every form of the score uses
-// it, so fused and replayed scores agree bit for bit.
+// Cheaper than the correctly rounded quotient.  Every form of the score
+// uses it, so where the visits' scores are summed in a fixed order (the
+// persistent and resident forms) fused and replayed scores agree bit for
+// bit; the phase and dataflow forms add them with atomics, in no fixed
+// order, so there the bins agree to rounding.
 __device__ __forceinline__ double null_quot(uint32_t m, double den) {
     double r = __builtin_amdgcn_rcp(den);
     double e = __builtin_fma(-den, r, 1.0);

@@ -3,6 +3,10 @@ and element-by-element comparisons."""
 import numpy as np
 
 RTOL_T = 1e-12
+# score bins: |GPU - oracle| <= SCORE_REL * (sum over the bin of the absolute
+# values of its terms, as the oracle reports them).  Scores are zero-mean
+# sums of O(1) terms, so a relative bound on the value itself is ill-posed.
+SCORE_REL = 1e-12
 
 
 def say(msg):
@@ -42,3 +46,23 @@ def assert_replica_equal(lat, rho, ora, gpu_rec=None, ora_rec=None, what=""):
     if gpu_rec is not None:
         assert_records_equal(gpu_rec, ora_rec, what)
     assert g.shape == (L, L)
+
+
+def oracle_score(kmco, desc, seed, rho, sweeps, every, pre=0, spins=None):
+    """The oracle's records, score bins and bin magnitudes (sums of absolute
+    terms) of one replica after `pre` unscored sweeps."""
+    o = oracle_for(kmco, desc, seed, rho, spins)
+    if pre:
+        o.run(pre, 1)
+    rec, sc, sa = o.run(sweeps, every, score_abs=True)
+    return o, rec, sc, sa
+
+
+def assert_score_close(gpu, ref, mag, what=""):
+    """Score bins within SCORE_REL of the bins' sums of absolute terms."""
+    gpu, ref, mag = (np.asarray(x, np.float64) for x in (gpu, ref, mag))
+    assert gpu.shape == ref.shape == mag.shape, (what, gpu.shape, ref.shape, mag.shape)
+    err = np.abs(gpu - ref)
+    bound = SCORE_REL * mag
+    bad = np.argwhere(err > bound)
+    assert bad.size == 0, (what, bad[:4], err[tuple(bad[0])], bound[tuple(bad[0])])

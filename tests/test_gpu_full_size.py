@@ -14,7 +14,8 @@ import pytest
 
 from oracle import closed_forms as cf
 from paper_1403_4674_amd import kmc, workloads
-from tests.gpu_helpers import assert_records_equal, oracle_for, say
+from tests.gpu_helpers import (assert_records_equal, assert_score_close, oracle_for,
+                               oracle_score, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +39,7 @@ def sample_per_L(descs, per_L, rng):
 
 def test_batched_4096_sampled_parity(torch_cuda, oracle_lib):
     seed, descs, _ = workloads.batched_4096()
-    sweeps = 12
+    sweeps = 20
     say(f"4096 replicas, {sweeps} sweeps, persistent (bench configuration)")
     lat = kmc.Lattice(descs, seed)
     lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
@@ -54,25 +55,26 @@ def test_batched_4096_sampled_parity(torch_cuda, oracle_lib):
 
 
 def test_differentiable_1024_sampled_parity(torch_cuda, oracle_lib):
-    seed, descs, _ = workloads.differentiable_1024()
-    sweeps, every = 10, 5
-    say(f"1024 replicas of 64^2 (tile {descs[0]['tile']}), fused score and replay")
+    seed, descs, run = workloads.differentiable_1024()
+    sweeps, every = 100, run["record_every"]
+    n_bins = sweeps // every
+    say(f"1024 replicas of 64^2 (tile {descs[0]['tile']}), {sweeps} sweeps, fused score "
+        f"and replay")
     lat = kmc.Lattice(descs, seed)
     lat.run(sweeps, every, kmc.F_PERSISTENT | kmc.F_SCORE)
-    fused = lat.score(2)
+    fused = lat.score(n_bins)
     rec = lat.records()
     rep = kmc.Lattice(descs, seed)
     rep.run(sweeps, every, kmc.F_PERSISTENT | kmc.F_CHECKPOINT)
-    replay = rep.score(2)
+    replay = rep.score(n_bins)
     assert np.array_equal(fused, replay)
-    ticks_per_bin = every * 64 * 64
+    assert np.array_equal(rec, rep.records())
     for rho in np.random.default_rng(1).choice(len(descs), 16, replace=False):
         rho = int(rho)
-        o = oracle_for(oracle_lib, descs[rho], seed, rho)
-        orec, sc = o.run(sweeps, every, score=True)
+        o, orec, sc, mag = oracle_score(oracle_lib, descs[rho], seed, rho, sweeps, every)
         assert np.array_equal(lat.spins(rho), o.spins()), rho
         assert_records_equal(rec[rho], orec, f"replica {rho}")
-        np.testing.assert_allclose(fused[rho], sc, rtol=1e-10, atol=1e-11 * ticks_per_bin)
+        assert_score_close(fused[rho], sc, mag, f"replica {rho}")
 
 
 def batch_mean(x, nb=20):

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 from paper_1403_4674_amd import kmc
-from tests.gpu_helpers import assert_records_equal, assert_replica_equal, oracle_for, say
+from tests.gpu_helpers import (assert_records_equal, assert_replica_equal, assert_score_close,
+                               oracle_for, oracle_score, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -88,13 +89,8 @@ def test_resident_score_fused_equals_replay_and_oracle(torch_cuda, oracle_lib):
     replay = r.score(sweeps // every)
     assert np.array_equal(fused, replay)
     for rho, d in enumerate(descs):
-        o = oracle_for(oracle_lib, d, 13, rho)
-        _, sc = o.run(sweeps, every, score=True)
-        nd = d["tile"] * (d.get("tile_rows") or d["tile"])
-        ticks = every * (d["L"] // d["tile"]) * (d["L"] // (d.get("tile_rows") or d["tile"])) \
-            * (d.get("steps_per_visit") or nd)
-        np.testing.assert_allclose(fused[rho], sc, rtol=1e-10, atol=1e-11 * ticks,
-                                   err_msg=f"replica {rho}")
+        _, _, sc, mag = oracle_score(oracle_lib, d, 13, rho, sweeps, every)
+        assert_score_close(fused[rho], sc, mag, f"replica {rho}")
 
 
 def test_resident_flag_and_shape_errors(torch_cuda):

@@ -124,3 +124,44 @@ def test_tick_slot_rejection_and_retry_streams(oracle_lib):
     retries = np.array(retries)
     assert 0.45 < (retries > 0).mean() < 0.55
     assert abs(low / 4000 - 0.5) < 0.03
+
+
+def init_lattice_py(seed, replica, L):
+    """The random start recomputed from the generator: site i (row-major) is
+    +1 when bit i % 32 of word (i / 32) % 4 of INIT-stream call i / 128
+    (counter (call, 1 << 24, 0, replica)) is set."""
+    out = np.empty(L * L, np.int8)
+    key = [seed & MASK, seed >> 32]
+    for call in range(-(-(L * L) // 128)):
+        words = philox_py([call, 1 << 24, 0, replica], key)
+        for i in range(call * 128, min(L * L, call * 128 + 128)):
+            out[i] = 1 if (words[(i >> 5) & 3] >> (i & 31)) & 1 else -1
+    return out.reshape(L, L)
+
+
+@pytest.mark.parametrize("L,seed,replica", [(20, 7, 0), (24, 0x1234_5678_9ABC_DEF0, 5),
+                                            (33, 2, 3)])
+def test_random_start_recomputed(oracle_lib, L, seed, replica):
+    r = oracle_lib.Replica(L, L if L % 2 else L // 2, T=2.0, seed=seed, replica=replica)
+    assert np.array_equal(r.spins(), init_lattice_py(seed, replica, L))
+
+
+def test_random_start_is_uniform_and_uncorrelated(oracle_lib):
+    """The random start is i.i.d. +-1 with probability 1/2: the fraction of
+    up spins, the nearest-neighbour bond averages along both axes and the
+    correlation between replicas are all zero within 4.5 standard errors, and
+    the 16 patterns of 2 x 2 blocks are uniform (chi-square)."""
+    L = 256
+    a = oracle_lib.Replica(L, 32, T=2.0, seed=9, replica=0).spins().astype(np.int64)
+    b = oracle_lib.Replica(L, 32, T=2.0, seed=9, replica=1).spins().astype(np.int64)
+    n = L * L
+    se = 1.0 / np.sqrt(n)
+    assert set(np.unique(a)) == {-1, 1}
+    assert abs(a.mean()) < 4.5 * se
+    assert abs((a * np.roll(a, 1, 0)).mean()) < 4.5 * se
+    assert abs((a * np.roll(a, 1, 1)).mean()) < 4.5 * se
+    assert abs((a * b).mean()) < 4.5 * se
+    blocks = ((a[0::2, 0::2] > 0) + 2 * (a[0::2, 1::2] > 0) + 4 * (a[1::2, 0::2] > 0)
+              + 8 * (a[1::2, 1::2] > 0))
+    counts = np.bincount(blocks.ravel(), minlength=16)
+    assert stats.chisquare(counts).pvalue > 1e-4
