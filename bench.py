@@ -5,16 +5,25 @@ One step = one schedule sweep of the 1024x1024 periodic Ising lattice cut
 into 32x32 domains (1024 domains, 4 colour phases of 256 domains each,
 N_I = 1024 ticks per visit, Metropolis, T = 2.269, random start): every
 domain visit, class bookkeeping, event selection, clock and the sweep
-record.  value = site updates (ticks, null ticks included) per second, with
-the sweep run as one dataflow launch (each visit starts once the visits of
-its neighbours that precede it in the schedule are done; KMC_F_FLOW).
+record.  value = site updates (ticks, null ticks included) per second over
+exactly --steps sweeps, with the sweeps run as dataflow launches (each visit
+starts once the visits of its neighbours that precede it in the schedule are
+done; KMC_F_FLOW).
 
-Extra measurements on the same line: the same workload as four phase
-launches per sweep, the batched persistent form (4096 ragged replicas), the
-backward score replay and fused score (1024 replicas of 64x64), the
-roofline of the dominant kernel, the serial CPU oracle on a bounded sample
-of the same workload (one core), and the oracle on the batch with one
-process per host core.
+Extra legs on the same line (none of them part of `value`):
+* plain_steady: the same workload over three 64-sweep launches, the
+  reference for every ratio against the plain kernel;
+* plain_phased: the same workload as four phase launches per sweep;
+* plain_T: the same lattice at T = 1.5 and T = 3.0;
+* quench_4096: the 4096x4096 quench lattice (64x64 domains, N_I = 4096);
+* small_NI: the 1024x1024 lattice at the paper's visit lengths
+  N_I in {1, 2, 5, 10} (Sec. 3, Table 1), where the kernel streams its tiles
+  and the HBM roofline is the one that applies;
+* batched: the persistent form on 4096 ragged replicas;
+* backward: the score replay and the fused score on 1024 replicas of 64x64;
+* parity: the timed plain form and the batched multi-slot form against the
+  oracle;
+* cpu_baseline / cpu_batched: the serial CPU oracle on bounded samples.
 """
 import argparse
 import json
@@ -27,48 +36,58 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Integer lane-operations per tick and per event that the method itself
-# requires (see the design notes): one Philox4x32-10 call per tick (20
-# 32x32->64 products = 40 multiplies, 40 XORs, 18 key additions) plus the
-# slot and 64-bit threshold test; per event the class prefix, the member
-# rank, five reclassifications and the count / rate-sum update.
-OPS_PER_TICK = 102
-OPS_PER_EVENT = 64
+# requires (not what the kernel spends): per tick 64 random bits (half a
+# Philox4x32-10 call: 10 rounds of one 32x32->64 product (2 multiplies), 2
+# XORs and the key additions, ~49 lane-ops) and the 64-bit test x < R (2);
+# per event the clock's 53 random bits (another half call, 49), the class
+# prefix and compare (~20), the member rank (~12), five reclassifications
+# (~20) and the count / rate-sum update (~12).  The FP64 log and divide of
+# the clock are not counted.
+OPS_PER_TICK = 51
+OPS_PER_EVENT = 64 + 49
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer lane-operations/s
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X HBM3E
+HBM_PEAK = 8.0e12
 
-# HBM bytes of one launch of each plain-form kernel: rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
-# counter reads for a 1 GiB device copy (profiles/copy_calibration_1GiB.md,
-# profiles/k_flow_ising2d_L1024_tile32_plain.md,
-# profiles/k_phase_ising2d_L1024_tile32_plain.md).  Valid only for the
-# kernel source the counters were taken on; reported as null otherwise.
-PLAIN_TRAFFIC = {
-    "kernel_source_sha256": "ebae7473953b539bc3255dafa34b7fdd232a7132252188d1983b1111d503e395",
+# HBM bytes per sweep of the plain-form kernels on each plain workload:
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, divided by
+# the sweeps of the dispatch), each scaled by what the counter reads for a
+# 1 GiB device copy (profiles/copy_calibration_1GiB.md; the per-workload
+# summaries in profiles/ name the command).  Valid only for the kernel source
+# the counters were taken on (sha256 of kmc_device.h); null otherwise.
+TRAFFIC = {
+    "kernel_source_sha256": None,
     "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
-    # k_flow: per sweep (the counter runs launch 40 sweeps per dispatch);
-    # k_phase: per launch (one colour phase)
-    "kib": {"k_flow<uint32_t,false,false>": (3400.95, 1218.22),
-            "k_phase<uint32_t,false,false>": (940.51, 288.0)},
+    # workload -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per sweep
+    "kib_per_sweep": {},
 }
-# algorithmic bytes per colour phase of the plain workload: each of the 256
-# domains reads its 32x32 int8 tile and 4 x 32 halo sites and writes the
-# tile back (a one-launch sweep covers four phases)
-PLAIN_ALG_BYTES_PER_PHASE = 256 * (2 * 32 * 32 + 4 * 32)
 
 
-def plain_traffic(kernel, sweeps_per_launch=1.0):
+def kernel_source_sha():
     import hashlib
-    t = PLAIN_TRAFFIC
-    if kernel not in t["kib"]:
-        return None
     src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", "kmc_device.h")
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["kernel_source_sha256"]:
-            return None
-    fetch, write = t["kib"][kernel]
-    per = (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
-    # dataflow launches: the counters are kept per sweep
-    return per * (sweeps_per_launch if kernel.startswith("k_flow") else 1.0)
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_sweep(workload):
+    """Calibrated HBM bytes per sweep measured for `workload`, or None."""
+    t = TRAFFIC
+    if workload not in t["kib_per_sweep"] or t["kernel_source_sha256"] != kernel_source_sha():
+        return None
+    fetch, write = t["kib_per_sweep"][workload]
+    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+
+
+def alg_bytes_per_sweep(d):
+    """Algorithmic HBM bytes of one sweep of a plain lattice: every visit
+    reads its int8 tile and the 2 (Bx + By) halo sites and writes the tile
+    back (tables, records and counters are negligible)."""
+    L, bx = d["L"], d["tile"]
+    by = d.get("tile_rows") or bx
+    nd = (L // bx) * (L // by)
+    return nd * (2 * bx * by + 2 * (bx + by))
 
 
 def timed(fn, stream):
@@ -83,34 +102,74 @@ def timed(fn, stream):
     return a.elapsed_time(b) / 1e3
 
 
-def plain(args, kmc, workloads, phased=False, steps=None):
-    """The 1024^2 lattice, one sweep per step.  Default form: one dataflow
-    launch per sweep (KMC_F_FLOW); phased: four colour-phase launches."""
+def workload_name(d, form="flow"):
+    T = f"{d['T']:g}"
+    return (f"ising2d_L{d['L']}_tile{d['tile']}_NI{d['steps_per_visit']}_T{T}_metropolis_"
+            f"{'plain' if form == 'flow' else 'plain_phased'}")
+
+
+def plain(args, kmc, desc, seed, steps, warmup, phased=False, graph=False):
+    """One plain lattice, one sweep per step, in the dataflow form (launches
+    of up to 64 sweeps, KMC_F_FLOW) or as four colour-phase launches per
+    sweep.  HIP events on the context stream bracket every launch of the hot
+    kernel inside the timed region (KMC_F_TIMING), unless graph."""
     import torch
-    steps = args.steps if steps is None else steps
-    seed, descs, _ = workloads.single_1024(2.269)
-    d = descs[0]
-    lat = kmc.Lattice(descs, seed)
+    d = desc
+    lat = kmc.Lattice([d], seed)
     stream = torch.cuda.current_stream()
-    # without a graph, HIP events on the context stream bracket every launch
-    # of the hot kernel inside the timed region (KMC_F_TIMING)
-    flags = (kmc.F_GRAPH if args.graph else kmc.F_TIMING) | (0 if phased else kmc.F_FLOW)
-    lat.run(args.warmup, 1, flags)
+    flags = (kmc.F_GRAPH if graph else kmc.F_TIMING) | (0 if phased else kmc.F_FLOW)
+    if warmup:
+        lat.run(warmup, warmup, flags)
     torch.cuda.synchronize()
-    if not args.graph:
+    if not graph:
         lat.timing()
-    ev0 = lat.records()[0][-1]["events"] if args.warmup else 0
-    sec = timed(lambda: lat.run(steps, 1, flags), stream)
-    kernel_ms, launches = (lat.timing() if not args.graph
+    ev0 = int(lat.records()[0][-1]["events"]) if warmup else 0
+    sec = timed(lambda: lat.run(steps, steps, flags), stream)
+    kernel_ms, launches = (lat.timing() if not graph
                            else (None, (4 if phased else 1) * steps))
-    rec = lat.records()[0]
-    events = int(rec[-1]["events"] - ev0)
-    ticks = steps * d["L"] ** 2
+    events = int(lat.records()[0][-1]["events"]) - ev0
+    nd = (d["L"] // d["tile"]) ** 2
+    ticks = steps * nd * d["steps_per_visit"]
     lat.close()
-    return dict(sec=sec, ticks=ticks, events=events, launches=launches,
-                kernel_sec=None if kernel_ms is None else kernel_ms / 1e3,
-                desc=d, seed=seed, phased=phased,
-                kernel="k_phase<uint32_t,false,false>" if phased else "k_flow<uint32_t,false,false>")
+    kernel_sec = kernel_ms / 1e3 if kernel_ms is not None else sec
+    kern = ("k_phase" if phased else "k_flow") + (
+        "<uint64_t,false,false>" if d["tile"] > 32 else "<uint32_t,false,false>")
+    return dict(sec=sec, ticks=ticks, events=events, launches=launches, steps=steps,
+                kernel_sec=kernel_sec, timing="hip_events_per_launch" if kernel_ms is not None
+                else "timed_region_over_launches", desc=d, seed=seed, phased=phased,
+                kernel=kern, workload=workload_name(d, "phased" if phased else "flow"))
+
+
+def roofline(p):
+    """Both rooflines of a plain leg: the lane-op count of the method (ALU)
+    and its algorithmic HBM bytes, over the summed duration of the timed
+    launches of its kernel."""
+    ops = OPS_PER_TICK * p["ticks"] + OPS_PER_EVENT * p["events"]
+    alg = alg_bytes_per_sweep(p["desc"]) * p["steps"]
+    tr = traffic_per_sweep(p["workload"])
+    ks = p["kernel_sec"]
+    return {
+        "kernel": p["kernel"],
+        "per_launch_ms": ks * 1e3 / p["launches"],
+        "launches": p["launches"],
+        "sweeps_per_launch": p["steps"] / p["launches"],
+        "launch_timing": p["timing"],
+        "alu": {"achieved": ops / ks / 1e12, "peak": ALU_PEAK_LANE_OPS / 1e12,
+                "unit": "Tlane-op/s", "frac": ops / ks / ALU_PEAK_LANE_OPS,
+                "ops_per_launch": ops / p["launches"]},
+        "hbm": {"achieved": alg / ks / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": alg / ks / HBM_PEAK, "algorithmic_bytes_per_launch": alg / p["launches"],
+                "traffic": None if tr is None else tr * p["steps"] / p["launches"],
+                "traffic_unit": "B/launch"},
+    }
+
+
+def leg(p, extra=None):
+    out = {"value": p["ticks"] / p["sec"], "unit": "site-updates/s", "steps": p["steps"],
+           "ms_per_step": p["sec"] * 1e3 / p["steps"], "events_per_s": p["events"] / p["sec"],
+           "workload": p["workload"], "roofline": roofline(p)}
+    out.update(extra or {})
+    return out
 
 
 def parse_tiles(text):
@@ -155,23 +214,43 @@ def backward(args, kmc, workloads):
                 replicas=len(descs), sweeps=n)
 
 
-def parity_prefix(kmc, workloads):
-    """Two sweeps of the benchmark workload checked against the oracle."""
+def parity(kmc, workloads):
+    """The timed forms against the oracle: two sweeps of the plain workload as
+    one dataflow launch (KMC_F_FLOW), and three sweeps of the 4096-replica
+    batch in the persistent form the batched leg times, with one replica of
+    each lattice side compared."""
     import numpy as np
 
     from oracle import kmco
+
+    def oracle(d, seed, rho):
+        return kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
+                            steps_per_visit=d["steps_per_visit"], seed=seed, replica=rho,
+                            tile_rows=d.get("tile_rows", 0))
+
+    def same(g, r, sg, so):
+        ok = all(np.array_equal(g[f], r[f]) for f in ("sweep", "M", "B", "events", "steps"))
+        return bool(ok and np.array_equal(sg, so) and np.allclose(g["t"], r["t"], rtol=1e-12))
+
     seed, descs, _ = workloads.single_1024(2.269)
-    d = descs[0]
     lat = kmc.Lattice(descs, seed)
-    lat.run(2, 1)
-    g, s = lat.records()[0], lat.spins(0)
+    lat.run(2, 1, kmc.F_FLOW)
+    o = oracle(descs[0], seed, 0)
+    ok_plain = same(lat.records()[0], o.run(2, 1), lat.spins(0), o.spins())
     lat.close()
-    o = kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
-                     steps_per_visit=d["steps_per_visit"], seed=seed, replica=0)
-    r = o.run(2, 1)
-    ok = all(np.array_equal(g[f], r[f]) for f in ("M", "B", "events", "steps"))
-    ok = ok and np.array_equal(s, o.spins()) and np.allclose(g["t"], r["t"], rtol=1e-12)
-    return bool(ok)
+    seed, descs, _ = workloads.batched_4096()
+    lat = kmc.Lattice(descs, seed)
+    lat.run(3, 1, kmc.F_PERSISTENT)
+    rec = lat.records()
+    picks = sorted({d["L"]: rho for rho, d in enumerate(descs)}.values())
+    ok_batch = True
+    for rho in picks:
+        o = oracle(descs[rho], seed, rho)
+        ok_batch = ok_batch and same(rec[rho], o.run(3, 1), lat.spins(rho), o.spins())
+    lat.close()
+    return {"plain_flow_2_sweeps": ok_plain,
+            f"batched_persistent_3_sweeps_{len(picks)}_replicas": ok_batch,
+            "bit_exact": ok_plain and ok_batch}
 
 
 def cpu_baseline(budget_s):
@@ -254,6 +333,14 @@ def copy_probe(nbytes):
     return nbytes
 
 
+# the paper's visit lengths (Sec. 3, Table 1)
+SMALL_NI = (1, 2, 5, 10)
+
+
+def small_ni_desc(d, ni):
+    return dict(d, steps_per_visit=ni)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,14 +348,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--graph", action="store_true", help="replay sweeps from a hipGraph")
     ap.add_argument("--phased", action="store_true",
-                    help="plain form as four phase launches per sweep (default: one "
-                         "dataflow launch per sweep, KMC_F_FLOW)")
+                    help="plain form as four phase launches per sweep (default: dataflow "
+                         "launches of up to 64 sweeps, KMC_F_FLOW)")
     ap.add_argument("--batched-sweeps", type=int, default=40)
     ap.add_argument("--grad-sweeps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mode", default="all",
-                    choices=["all", "plain", "batched", "backward", "copy"],
+                    choices=["all", "plain", "small_ni", "quench", "batched", "backward",
+                             "copy"],
                     help="all: the full line; the others run one part (for profiling)")
+    ap.add_argument("--ni", type=int, default=0,
+                    help="--mode small_ni: run only this N_I (default: 1, 2, 5, 10)")
     ap.add_argument("--no-extras", action="store_true", help="same as --mode plain")
     ap.add_argument("--tiles", default="", help="batched workload tiles, e.g. 16:8,24:12")
     ap.add_argument("--flags", type=int, default=0, help="extra kmc_run_schedule flags (batched)")
@@ -289,6 +379,8 @@ def main():
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
 
+    seed2, d2s, _ = workloads.single_1024(2.269)
+    d2 = d2s[0]
     if args.mode == "copy":
         n = copy_probe(1 << 30)
         print(json.dumps({"copy_probe_bytes": n}), flush=True)
@@ -302,17 +394,21 @@ def main():
         g = backward(args, kmc, workloads)
         print(json.dumps({"backward": g}), flush=True)
         return
+    if args.mode == "small_ni":
+        for ni in ([args.ni] if args.ni else SMALL_NI):
+            p = plain(args, kmc, small_ni_desc(d2, ni), seed2, args.steps, args.warmup)
+            print(json.dumps({f"NI{ni}": leg(p)}), flush=True)
+        return
+    if args.mode == "quench":
+        seed3, d3s, _ = workloads.quench_4096()
+        p = plain(args, kmc, d3s[0], seed3, args.steps, args.warmup)
+        print(json.dumps({"quench_4096": leg(p)}), flush=True)
+        return
 
-    p = plain(args, kmc, workloads, phased=args.phased)
+    p = plain(args, kmc, d2, seed2, args.steps, args.warmup, phased=args.phased,
+              graph=args.graph)
     value = p["ticks"] / p["sec"]
-    # average duration of one phase-kernel launch: from the HIP events around
-    # each launch; with --graph, the timed region over the launch count
-    kernel_sec = p["kernel_sec"] if p["kernel_sec"] is not None else p["sec"]
-    per_launch = kernel_sec / p["launches"]
-    sweeps_per_launch = 0.25 if p["phased"] else args.steps / p["launches"]
-    d = p["desc"]
-    ops = OPS_PER_TICK * p["ticks"] + OPS_PER_EVENT * p["events"]
-    achieved = ops / kernel_sec
+    rl = roofline(p)
     line = {
         "metric": "site-updates/s (plain vs batched replicas) + backward overhead at "
                   "bit-exact oracle match",
@@ -328,45 +424,50 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain",
-                   "L": d["L"], "tile": d["tile"], "steps_per_visit": d["steps_per_visit"],
-                   "T": d["T"], "seed": p["seed"], "graph": bool(args.graph),
+                   "L": d2["L"], "tile": d2["tile"], "steps_per_visit": d2["steps_per_visit"],
+                   "T": d2["T"], "seed": seed2, "graph": bool(args.graph),
                    "form": "phase_launches" if p["phased"]
                    else "dataflow_launches_of_up_to_64_sweeps"},
         "events_per_s": p["events"] / p["sec"],
-        "roofline": {
-            "bound": "alu",
-            "kernel": p["kernel"],
-            "achieved": achieved / 1e12,
-            "peak": ALU_PEAK_LANE_OPS / 1e12,
-            "unit": "Tlane-op/s",
-            "frac": achieved / ALU_PEAK_LANE_OPS,
-            "traffic": plain_traffic(p["kernel"], sweeps_per_launch),
-            "traffic_unit": "B/launch",
-            "algorithmic_bytes_per_launch": PLAIN_ALG_BYTES_PER_PHASE * 4 * sweeps_per_launch,
-            "sweeps_per_launch": sweeps_per_launch,
-            "per_launch_ms": per_launch * 1e3,
-            "launches": p["launches"],
-            "ops_per_launch": ops / p["launches"],
-            "launch_timing": "hip_events_per_launch" if p["kernel_sec"] is not None
-                             else "timed_region_over_launches",
-        },
+        # the dominant kernel is bound by its serial event chain (instruction
+        # issue and latency): "alu", with the HBM fraction of its algorithmic
+        # bytes beside it
+        "roofline": {"bound": "alu", "kernel": p["kernel"],
+                     "achieved": rl["alu"]["achieved"], "peak": rl["alu"]["peak"],
+                     "unit": rl["alu"]["unit"], "frac": rl["alu"]["frac"],
+                     "traffic": rl["hbm"]["traffic"], "traffic_unit": "B/launch",
+                     "hbm_frac": rl["hbm"]["frac"], "hbm_achieved_GBps": rl["hbm"]["achieved"],
+                     "algorithmic_bytes_per_launch": rl["hbm"]["algorithmic_bytes_per_launch"],
+                     "ops_per_launch": rl["alu"]["ops_per_launch"],
+                     "per_launch_ms": rl["per_launch_ms"], "launches": rl["launches"],
+                     "sweeps_per_launch": rl["sweeps_per_launch"],
+                     "launch_timing": rl["launch_timing"]},
     }
     if args.mode == "all":
-        if not args.phased:  # the four-launches-per-sweep form of the same workload
-            q = plain(args, kmc, workloads, phased=True, steps=max(args.steps // 2, 1))
-            line["plain_phased"] = {"value": q["ticks"] / q["sec"], "unit": "site-updates/s",
-                                    "steps": max(args.steps // 2, 1),
-                                    "kernel": q["kernel"],
-                                    "per_launch_ms": q["kernel_sec"] * 1e3 / q["launches"],
-                                    "flow_speedup": value / (q["ticks"] / q["sec"])}
+        # the reference for every ratio: the same workload at its steady state
+        # (three full 64-sweep launches after the warm-up)
+        st = plain(args, kmc, d2, seed2, 3 * kmc.FLOW_MAX_SWEEPS, max(args.warmup, 40))
+        plain_ref = st["ticks"] / st["sec"]
+        line["plain_steady"] = leg(st)
+        q = plain(args, kmc, d2, seed2, 64, 16, phased=True)
+        line["plain_phased"] = leg(q, {"flow_speedup": plain_ref / (q["ticks"] / q["sec"])})
+        line["plain_T"] = {}
+        for T in (1.5, 3.0):
+            sT, dTs, _ = workloads.single_1024(T)
+            line["plain_T"][f"T{T:g}"] = leg(plain(args, kmc, dTs[0], sT, 128, 16))
+        seed3, d3s, _ = workloads.quench_4096()
+        line["quench_4096"] = leg(plain(args, kmc, d3s[0], seed3, 20, 4))
+        line["small_NI"] = {}
+        for ni in SMALL_NI:
+            line["small_NI"][f"NI{ni}"] = leg(
+                plain(args, kmc, small_ni_desc(d2, ni), seed2, 3 * kmc.FLOW_MAX_SWEEPS, 16))
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
         b_ops = OPS_PER_TICK * b["ticks"] + OPS_PER_EVENT * b["events"]
         line["batched"] = {"value": b["ticks"] / b["sec"], "unit": "site-updates/s",
                            "replicas": b["replicas"], "sweeps": b["sweeps"],
-                           "vs_plain": (b["ticks"] / b["sec"]) / value,
-                           "vs_plain_phased": (b["ticks"] / b["sec"])
-                           / line.get("plain_phased", {"value": value})["value"],
+                           "vs_plain_steady": (b["ticks"] / b["sec"]) / plain_ref,
+                           "vs_plain_phased": (b["ticks"] / b["sec"]) / (q["ticks"] / q["sec"]),
                            "roofline": {"bound": "alu", "kernel": "k_persistent_multi<false>",
                                         "achieved": b_ops / b["kernel_sec"] / 1e12,
                                         "peak": ALU_PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
@@ -376,27 +477,24 @@ def main():
         line["backward"] = {"fwd_site_updates_per_s": g["ticks"] / g["fwd"],
                             "overhead": g["overhead"], "replicas": g["replicas"],
                             "sweeps": g["sweeps"],
-                            "fwd_plus_bwd_vs_plain": (g["ticks"] / (g["fwd"] + g["bwd"]))
-                            / value,
+                            "fwd_plus_bwd_vs_plain_steady": (g["ticks"] / (g["fwd"] + g["bwd"]))
+                            / plain_ref,
                             "fused_overhead": g["fused_overhead"],
                             "fused_site_updates_per_s": g["ticks"] / g["fused"],
-                            "fused_vs_plain": (g["ticks"] / g["fused"]) / value,
+                            "fused_vs_plain_steady": (g["ticks"] / g["fused"]) / plain_ref,
                             "fused_vs_plain_phased": (g["ticks"] / g["fused"])
-                            / line.get("plain_phased", {"value": value})["value"]}
+                            / (q["ticks"] / q["sec"])}
         # the same comparison counted in replicas advanced by one sweep per
         # second (the plain workload is one replica of 1024^2); site-updates/s
         # above is the stricter unit, as the batches hold smaller replicas
-        plain_rs = value / (1024 * 1024)
+        plain_rs = plain_ref / (1024 * 1024)
         line["replica_sweeps_per_s"] = {
-            "plain": plain_rs,
+            "plain_steady": plain_rs,
             "batched": b["replicas"] * b["sweeps"] / b["sec"],
             "fused_score": g["replicas"] * g["sweeps"] / g["fused"],
         }
-        line["replica_sweeps_per_s"]["batched_vs_plain"] = (
-            line["replica_sweeps_per_s"]["batched"] / plain_rs)
-        line["replica_sweeps_per_s"]["fused_score_vs_plain"] = (
-            line["replica_sweeps_per_s"]["fused_score"] / plain_rs)
-        line["parity_prefix_bit_exact"] = parity_prefix(kmc, workloads)
+        line["parity"] = parity(kmc, workloads)
+        line["parity_prefix_bit_exact"] = line["parity"]["bit_exact"]
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         line["cpu_batched"] = cpu_batched(args.cpu_seconds * 2 / 3)
         line["batched"]["vs_cpu_batched"] = line["batched"]["value"] / line["cpu_batched"]["value"]
