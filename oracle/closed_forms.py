@@ -1,4 +1,6 @@
-"""Closed forms for the periodic 2D Ising model (test infrastructure only).
+"""Closed forms for the periodic Ising model (test infrastructure only).
+
+* The periodic ring (the paper's 1D system): transfer-matrix free energy.
 
 * Onsager (1944) energy per site and Yang (1952) spontaneous magnetisation
   of the infinite square lattice, J = 1, k_B = 1.
@@ -106,3 +108,30 @@ def kaufman_energy_std(T, L, J=1.0, dK=1e-4):
     d2 = (-f(K + 2 * dK) + 16 * f(K + dK) - 30 * f(K) + 16 * f(K - dK)
           - f(K - 2 * dK)) / (12 * dK * dK)
     return J * math.sqrt(d2) / (L * L)
+
+
+def ring_energy(N, T, J=1.0, h=0.0):
+    """Mean energy <H> of the periodic Ising ring of N sites (the paper's 1D
+    system, Sec. 3.1), H = -J sum s_i s_{i+1} - h sum s_i, from the 2 x 2
+    transfer matrix V_{s s'} = exp(K s s' + (h/2T)(s + s')), K = J/T
+    (Kramers-Wannier): Z = lam_+^N + lam_-^N with lam the eigenvalues of V,
+    and <H> = T^2 d ln Z/dT, here by a central difference in 1/T."""
+    def log_z(beta):
+        a = beta * J
+        b = beta * h
+        disc = math.sqrt(math.exp(2 * a) * math.sinh(b) ** 2 + math.exp(-2 * a))
+        lp = math.exp(a) * math.cosh(b) + disc
+        lm = math.exp(a) * math.cosh(b) - disc
+        # lam_-^N may be negative for odd N when lam_- < 0
+        return N * math.log(lp) + math.log1p((lm / lp) ** N)
+
+    beta, d = 1.0 / T, 1e-6
+    return -(log_z(beta + d) - log_z(beta - d)) / (2 * d)
+
+
+def ring_energy_std(N, T, J=1.0, h=0.0, d=1e-4):
+    """Standard deviation of H on the ring: Var(H) = d^2 ln Z/d beta^2."""
+    beta = 1.0 / T
+    e = lambda b: ring_energy(N, 1.0 / b, J, h)
+    var = -(e(beta + d) - e(beta - d)) / (2 * d)
+    return math.sqrt(max(var, 0.0))

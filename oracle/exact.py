@@ -175,3 +175,84 @@ def perm_rank(perm):
         rank += a * math.factorial(len(perm) - 1 - i)
         avail.pop(a)
     return rank
+
+
+# ------------------------------------------------------------------ the ring
+#
+# The paper's 1D system (Sec. 3.1): a periodic ring of N sites, site i with
+# the two neighbours i - 1 and i + 1, cut into N_D domains of B consecutive
+# sites (Eq. (1D partitions)).  State index bit i set when spin i is +1.
+
+def ring_spins(N):
+    idx = np.arange(1 << N, dtype=np.int64)
+    return (2 * ((idx[:, None] >> np.arange(N)[None, :]) & 1) - 1).astype(np.int8)
+
+
+def ring_boltzmann(N, J, h, T):
+    """pi over the 2^N ring states, with M and the bond sum B = sum s_i s_{i+1}."""
+    s = ring_spins(N).astype(np.int64)
+    M = s.sum(axis=1)
+    B = (s * np.roll(s, -1, axis=1)).sum(axis=1)
+    E = -J * B - h * M
+    a = -E / T
+    p = np.exp(a - a.max())
+    return p / p.sum(), M, B, E
+
+
+class RingTickKernel:
+    """One tick of a ring domain: site i of the domain's n_d sites is chosen
+    with probability 1/n_d and flipped with probability w (two neighbours)."""
+
+    def __init__(self, N, sites, J, h, T, model=0, quantise=False):
+        S = ring_spins(N).astype(np.float64)
+        self.N, self.sites = N, list(sites)
+        nd = len(self.sites)
+        self.flip_prob = []
+        for i in self.sites:
+            n = S[:, (i - 1) % N] + S[:, (i + 1) % N]
+            dE = 2.0 * S[:, i] * (J * n + h)
+            w = rate(dE, T, model)
+            if quantise:
+                w = np.minimum(np.floor(w * 2.0 ** 32 + 0.5), 2.0 ** 32) / 2.0 ** 32
+            self.flip_prob.append(w / nd)
+
+    def apply(self, p, times=1):
+        idx = np.arange(1 << self.N)
+        for _ in range(times):
+            out = p.copy()
+            for i, q in zip(self.sites, self.flip_prob):
+                moved = q * p
+                out -= moved
+                out[idx ^ (1 << i)] += moved
+            p = out
+        return p
+
+    def apply_transpose(self, v, times=1):
+        idx = np.arange(1 << self.N)
+        for _ in range(times):
+            out = v.copy()
+            for i, q in zip(self.sites, self.flip_prob):
+                out += q * (v[idx ^ (1 << i)] - v)
+            v = out
+        return v
+
+
+def ring_partition(N, B):
+    """Domains of B consecutive sites, their colours along the ring (one
+    colour for one domain, t mod 2 for an even count, t mod 2 with the last
+    domain given a third colour for an odd count) and the colour count."""
+    n = N // B
+    doms = [list(range(t * B, (t + 1) * B)) for t in range(n)]
+    cols = [0 if n == 1 else (2 if n % 2 and t == n - 1 else t % 2) for t in range(n)]
+    return doms, cols, 1 if n == 1 else (3 if n % 2 else 2)
+
+
+class RingSweepOperator(SweepOperator):
+    """T_PAR of the ring: the mixture over all orders of its colours (or the
+    palindrome), N_I ticks per domain visit (Eq. (1D partitions))."""
+
+    def __init__(self, N, B, J, h, T, model=0, NI=None, quantise=False, palindrome=False):
+        self.doms, self.cols, self.ncol = ring_partition(N, B)
+        self.kern = [RingTickKernel(N, d, J, h, T, model, quantise) for d in self.doms]
+        self.NI = NI if NI else B
+        self.palindrome = palindrome

@@ -40,6 +40,11 @@
  *      d ln(1 - R_w/n_d)/d theta = -R'_w/(n_d - R_w), R'_w = sum_c n_c w_c g_c,
  *      using the unquantised w.  The paper has no score; this is the
  *      likelihood ratio of the chain it defines.
+ *  R3b The paper's 1D system (Sec. 3.1, Eq. (1D partitions)) is a periodic
+ *      ring of L sites cut into domains of B consecutive sites; a site has
+ *      the two neighbours left and right, so its class is 5*[s=+1] + k with
+ *      k in 0..2 and dE = 2 s (J (2k - 2) + h).  The domains along the ring
+ *      are coloured like one axis of the square lattice.
  *  R6  Random numbers: Philox4x32-10, key = (seed low, seed high),
  *      counter = (tick, domain | visit<<20 | stream<<24, sweep, replica).
  *      Word 1 gives the slot (Lemire multiply with rejection, retried on
@@ -95,16 +100,17 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
 
 /* ------------------------------------------------------------ rate table */
 
-int kmco_rates(double J, double h, double T, int32_t model,
-               uint64_t r[10], double w[10], double gJ[10], double gh[10])
+int kmco_rates_z(double J, double h, double T, int32_t model, int32_t z,
+                 uint64_t r[10], double w[10], double gJ[10], double gh[10])
 {
     if (!(T > 0.0) || !isfinite(T) || !isfinite(J) || !isfinite(h)) return -1;
     if (model != KMCO_METROPOLIS && model != KMCO_BARKER) return -1;
+    if (z != 2 && z != 4) return -1;
     for (int c = 0; c < 10; ++c) {
         int up = c / 5;                 /* 1 if the site spin is +1      */
         int k = c % 5;                  /* number of up neighbours       */
         double s = up ? 1.0 : -1.0;
-        double n = (double)(2 * k - 4); /* neighbour sum                 */
+        double n = (double)(2 * k - z); /* neighbour sum                 */
         double dE = 2.0 * s * (J * n + h);
         double dEdJ = 2.0 * s * n;
         double dEdh = 2.0 * s;
@@ -129,6 +135,12 @@ int kmco_rates(double J, double h, double T, int32_t model,
         gh[c] = dlogw_ddE * dEdh;
     }
     return 0;
+}
+
+int kmco_rates(double J, double h, double T, int32_t model,
+               uint64_t r[10], double w[10], double gJ[10], double gh[10])
+{
+    return kmco_rates_z(J, h, T, model, 4, r, w, gJ, gh);
 }
 
 /* -------------------------------------------------------------- schedule */
@@ -214,6 +226,8 @@ uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
 
 struct kmco_state {
     int L, Bx, By, NTx, NTy, ND, nd, NI, sched, model;
+    int Ly;                /* lattice rows: L, or 1 for the ring          */
+    int z;                 /* neighbours per site: 4, or 2 on the ring    */
     int ncol;              /* colours of the domain grid                  */
     int32_t *colour;       /* [ND]                                        */
     double J, h, T;
@@ -238,15 +252,17 @@ static inline int wrap(int a, int L) { a %= L; return a < 0 ? a + L : a; }
 
 static inline int8_t spin_at(const kmco_state *s, int y, int x)
 {
-    return s->spin[wrap(y, s->L) * s->L + wrap(x, s->L)];
+    return s->spin[wrap(y, s->Ly) * s->L + wrap(x, s->L)];
 }
 
-/* Class of lattice site (y, x): 5*[spin up] + number of up neighbours. */
+/* Class of lattice site (y, x): 5*[spin up] + number of up neighbours (4 on
+ * the square lattice; left and right on the ring). */
 static int site_class(const kmco_state *s, int y, int x)
 {
     int up = spin_at(s, y, x) > 0;
-    int k = (spin_at(s, y - 1, x) > 0) + (spin_at(s, y + 1, x) > 0) +
-            (spin_at(s, y, x - 1) > 0) + (spin_at(s, y, x + 1) > 0);
+    int k = (spin_at(s, y, x - 1) > 0) + (spin_at(s, y, x + 1) > 0);
+    if (s->z == 4)
+        k += (spin_at(s, y - 1, x) > 0) + (spin_at(s, y + 1, x) > 0);
     return 5 * up + k;
 }
 
@@ -258,7 +274,10 @@ kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
                         const int8_t *given)
 {
     if (!d || d->L < 1 || d->tile < 1 || d->L % d->tile) return NULL;
-    const int By = d->tile_rows ? d->tile_rows : d->tile;
+    const int ring = d->dims == 1;
+    if (d->dims != 0 && d->dims != 1 && d->dims != 2) return NULL;
+    if (ring && d->tile_rows > 1) return NULL;
+    const int By = ring ? 1 : (d->tile_rows ? d->tile_rows : d->tile);
     if (By < 1 || d->L % By) return NULL;
     if (d->steps_per_visit < 0) return NULL;
     if (d->schedule != KMCO_SCHED_RANDOM_PERM &&
@@ -266,18 +285,20 @@ kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
     kmco_state *s = (kmco_state *)calloc(1, sizeof(*s));
     if (!s) return NULL;
     s->L = d->L; s->Bx = d->tile; s->By = By;
-    s->NTx = d->L / d->tile; s->NTy = d->L / By;
+    s->Ly = ring ? 1 : d->L;
+    s->z = ring ? 2 : 4;
+    s->NTx = d->L / d->tile; s->NTy = s->Ly / By;
     s->ND = s->NTx * s->NTy;
     s->nd = s->Bx * s->By;
     s->NI = d->steps_per_visit ? d->steps_per_visit : s->nd;
     s->sched = d->schedule; s->model = d->rate_model;
     s->J = d->J; s->h = d->h; s->T = d->T;
     s->seed = seed; s->replica = replica;
-    if (kmco_rates(s->J, s->h, s->T, s->model, s->r, s->w, s->gJ, s->gh)) {
+    if (kmco_rates_z(s->J, s->h, s->T, s->model, s->z, s->r, s->w, s->gJ, s->gh)) {
         free(s);
         return NULL;
     }
-    size_t N = (size_t)s->L * s->L;
+    size_t N = (size_t)s->L * s->Ly;
     s->spin = (int8_t *)malloc(N);
     s->clk_sum = (double *)calloc(s->ND, sizeof(double));
     s->clk_comp = (double *)calloc(s->ND, sizeof(double));
@@ -502,10 +523,10 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
 
         /* the flipped site and its neighbours inside the domain change class */
         int aff[5], na = 0;
-        const int dy[5] = {0, -1, 1, 0, 0}, dx[5] = {0, 0, 0, -1, 1};
-        for (int a = 0; a < 5; ++a) {
-            int yy = wrap(gy + dy[a], L), xx = wrap(gx + dx[a], L);
-            int ry = wrap(yy - oy, L), rx = wrap(xx - ox, L);
+        const int dy[5] = {0, 0, 0, -1, 1}, dx[5] = {0, -1, 1, 0, 0};
+        for (int a = 0; a < 1 + s->z; ++a) {
+            int yy = wrap(gy + dy[a], s->Ly), xx = wrap(gx + dx[a], L);
+            int ry = wrap(yy - oy, s->Ly), rx = wrap(xx - ox, L);
             if (ry >= By || rx >= Bx) continue; /* halo site: frozen */
             int kk = ry * Bx + rx, dup = 0;
             for (int b = 0; b < na; ++b) dup |= aff[b] == kk;
@@ -538,11 +559,12 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
 static void observe(const kmco_state *s, kmco_record *r)
 {
     int64_t M = 0, Bs = 0;
-    for (int y = 0; y < s->L; ++y)
+    for (int y = 0; y < s->Ly; ++y)
         for (int x = 0; x < s->L; ++x) {
             int8_t v = spin_at(s, y, x);
             M += v;
-            Bs += v * (spin_at(s, y, x + 1) + spin_at(s, y + 1, x));
+            Bs += v * spin_at(s, y, x + 1);
+            if (s->z == 4) Bs += v * spin_at(s, y + 1, x);
         }
     double tot = 0.0;
     for (int d = 0; d < s->ND; ++d) tot += s->clk_sum[d] + s->clk_comp[d];
@@ -608,7 +630,7 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
 int kmco_get_spins(const kmco_state *s, int8_t *out)
 {
     if (!s || !out) return -1;
-    memcpy(out, s->spin, (size_t)s->L * s->L);
+    memcpy(out, s->spin, (size_t)s->L * s->Ly);
     return 0;
 }
 

@@ -11,6 +11,7 @@
  * for parallel kinetic Monte Carlo simulation"):
  *   - periodic 2D Ising energy, Appendix A, Eq. (Hamiltonian Definition),
  *     extended by a uniform field h:  H = -J sum_<ij> s_i s_j - h sum_i s_i;
+ *     or the same energy on a periodic ring (the paper's 1D system, Sec. 3.1);
  *   - single-site kernel with self-loops, Appendix A, Eq. (Glauber_TM):
  *     selection probability 1/n_d inside a domain, acceptance w (Barker form
  *     as printed, or Metropolis min(1, exp(-dE/T)));
@@ -48,6 +49,9 @@ typedef struct {
     int32_t schedule;        /* KMCO_SCHED_*                                */
     int32_t init;            /* KMCO_INIT_*                                 */
     int32_t tile_rows;       /* By: domain height, L % By == 0; 0 means Bx  */
+    int32_t dims;            /* 0 or 2: periodic L x L lattice; 1: periodic
+                                ring of L sites (Sec. 3.1), domains of
+                                `tile` sites, tile_rows 0 or 1              */
 } kmco_desc;
 
 typedef struct {
@@ -64,9 +68,13 @@ typedef struct kmco_state kmco_state;
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
 void kmco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
-/* Per-class rate table: class c = 5*[s=+1] + k, k = up-neighbour count. */
+/* Per-class rate table: class c = 5*[s=+1] + k, k = up-neighbour count,
+ * on the square lattice (4 neighbours).  kmco_rates_z is the same table for
+ * z neighbours (z = 2: the ring; classes with k > z are never occupied). */
 int kmco_rates(double J, double h, double T, int32_t model,
                uint64_t r[10], double w[10], double gJ[10], double gh[10]);
+int kmco_rates_z(double J, double h, double T, int32_t model, int32_t z,
+                 uint64_t r[10], double w[10], double gJ[10], double gh[10]);
 
 /* Index in [0, n_perm) of the colour permutation for (seed, replica, sweep);
  * n_perm = n_colours!.  kmco_schedule_index is the 4-colour case (24). */

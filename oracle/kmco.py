@@ -20,7 +20,7 @@ class Desc(C.Structure):
                 ("L", C.c_int32), ("tile", C.c_int32),
                 ("steps_per_visit", C.c_int32), ("rate_model", C.c_int32),
                 ("schedule", C.c_int32), ("init", C.c_int32),
-                ("tile_rows", C.c_int32)]
+                ("tile_rows", C.c_int32), ("dims", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -45,6 +45,8 @@ def lib():
         L.kmco_philox.argtypes = [P, P, P]
         L.kmco_rates.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32,
                                  P, P, P, P]
+        L.kmco_rates_z.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                   P, P, P, P]
         L.kmco_schedule_index.argtypes = [C.c_uint64, C.c_int32, C.c_int64]
         L.kmco_schedule_index.restype = C.c_int32
         L.kmco_perm_from_index.argtypes = [C.c_int32, P]
@@ -85,10 +87,11 @@ def philox(ctr, key):
     return o
 
 
-def rates(J, h, T, model=METROPOLIS):
+def rates(J, h, T, model=METROPOLIS, z=4):
+    """Class rate table for z neighbours (4: square lattice, 2: ring)."""
     r = np.zeros(10, np.uint64)
     w, gJ, gh = (np.zeros(10) for _ in range(3))
-    if lib().kmco_rates(J, h, T, model, _ptr(r), _ptr(w), _ptr(gJ), _ptr(gh)):
+    if lib().kmco_rates_z(J, h, T, model, z, _ptr(r), _ptr(w), _ptr(gJ), _ptr(gh)):
         raise ValueError("invalid rate parameters")
     return r, w, gJ, gh
 
@@ -130,13 +133,14 @@ class Replica:
 
     def __init__(self, L, tile, J=1.0, h=0.0, T=2.5, steps_per_visit=0,
                  rate_model=METROPOLIS, schedule=SCHED_RANDOM_PERM,
-                 init=INIT_RANDOM, seed=1, replica=0, spins=None, tile_rows=0):
+                 init=INIT_RANDOM, seed=1, replica=0, spins=None, tile_rows=0, dims=2):
         self.desc = Desc(J, h, T, L, tile, steps_per_visit, rate_model,
-                         schedule, init, tile_rows)
+                         schedule, init, tile_rows, dims)
         self.L, self.tile = L, tile
-        self.tile_rows = tile_rows or tile
+        self.ring = dims == 1
+        self.tile_rows = 1 if self.ring else (tile_rows or tile)
         self.nd = tile * self.tile_rows
-        self.ND = (L // tile) * (L // self.tile_rows)
+        self.ND = (L // tile) * ((1 if self.ring else L) // self.tile_rows)
         self.NI = steps_per_visit or self.nd
         given = None
         if spins is not None:
@@ -172,7 +176,7 @@ class Replica:
         return t.value, d.value
 
     def spins(self):
-        out = np.zeros((self.L, self.L), np.int8)
+        out = np.zeros((self.L,) if self.ring else (self.L, self.L), np.int8)
         lib().kmco_get_spins(self._h, _ptr(out))
         return out
 
