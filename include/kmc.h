@@ -172,6 +172,21 @@ kmc_status kmc_set_wait_limit(kmc_ctx *c, int64_t max_polls);
 kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
                             int64_t n_sweeps, uint32_t flags, void *hip_stream);
 
+/* kmc_exact_sweeps for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same propagation, with the three work vectors
+ * in a buffer inside the library, 3 * 2^16 doubles (1.5 MiB), which every
+ * device the library runs on holds until the process ends.  So L*L <= 16:
+ * larger lattices return KMC_EINVAL before anything is enqueued.  p, flags,
+ * hip_stream and the errors are those of kmc_exact_sweeps; the call
+ * allocates nothing.  Every call on one device shares that device's buffer:
+ * calls whose work overlaps on one device (on different streams, or from
+ * different threads, before the previous one has finished) race and give
+ * undefined results.  Each call writes every entry of the buffer it reads,
+ * so nothing carries over from the previous call. */
+kmc_status kmc_exact_sweeps_static(const kmc_replica_desc *d, double *p, int64_t n_sweeps,
+                                   uint32_t flags, void *hip_stream);
+
 /* Per-class rate table of one replica (Appendix A, Eq. (Glauber_TM)).
  * Class c = 5*[s=+1] + k, k = number of up neighbours (0..4), flip energy
  * dE = 2 s (J (2k-4) + h).  r[c] = min(2^32, floor(w 2^32 + 1/2)) is the Q32

@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "kmc.h"
@@ -671,81 +672,171 @@ extern "C" kmc_status kmc_set_wait_limit(kmc_ctx *c, int64_t max_polls) {
     return KMC_OK;
 }
 
+namespace {
+
+// Everything one exact propagation needs, built on the stack (no heap, no
+// device allocation): the domains with their colours, and the colour orders
+// the sweep mixes (all n! orders of at most 4 colours, or the palindrome).
+struct ExactPlan {
+    kmcdev::ExactDomain dom[kmcdev::kExactMaxSites];
+    int col[kmcdev::kExactMaxSites];
+    int n_dom = 0;
+    int orders[24][18];
+    int n_orders = 0, order_len = 0;
+    kmcdev::ExactRates R;
+    int NI = 0;
+    double inv_nd = 0.0;
+};
+
+// Validates d and fills the plan; KMC_OK, KMC_EINVAL or KMC_EUNSUPPORTED.
+kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, ExactPlan &P) {
+    validate(nullptr, *d, 0);  // throws Fail{KMC_EINVAL}
+    const int L = d->L, N = L * L;
+    if (N > max_sites) return KMC_EINVAL;
+    const int Bx = d->tile, By = tile_rows_of(*d), NTx = L / Bx, NTy = L / By;
+    const int cx = axis_colours(NTx), ncol = cx * axis_colours(NTy);
+    const bool pal = d->schedule == KMC_SCHED_PALINDROME;
+    if (!pal && ncol > 4) return KMC_EUNSUPPORTED;  // more than 4! orders to mix
+    uint64_t r[10];
+    double w[10], gJ[10], gh[10];
+    if (rate_table(d->J, d->h, d->T, d->rate_model, r, w, gJ, gh) != KMC_OK) return KMC_EINVAL;
+    for (int c = 0; c < 10; ++c)
+        P.R.w[c] = (flags & KMC_EXACT_QUANTISED) ? (double)r[c] * 0x1p-32 : w[c];
+    // domains (row-major over the grid, sites row-major inside)
+    auto axis_colour = [](int t, int n) { return n == 1 ? 0 : (n % 2 && t == n - 1) ? 2 : t % 2; };
+    P.n_dom = 0;
+    for (int ty = 0; ty < NTy; ++ty)
+        for (int tx = 0; tx < NTx; ++tx) {
+            kmcdev::ExactDomain &D = P.dom[P.n_dom];
+            std::memset(&D, 0, sizeof(D));
+            D.n = Bx * By;
+            for (int ly = 0; ly < By; ++ly)
+                for (int lx = 0; lx < Bx; ++lx) {
+                    const int a = ly * Bx + lx, y = ty * By + ly, x = tx * Bx + lx;
+                    D.site[a] = y * L + x;
+                    D.nb[a][0] = ((y + L - 1) % L) * L + x;
+                    D.nb[a][1] = ((y + 1) % L) * L + x;
+                    D.nb[a][2] = y * L + (x + L - 1) % L;
+                    D.nb[a][3] = y * L + (x + 1) % L;
+                }
+            P.col[P.n_dom++] = axis_colour(tx, NTx) + cx * axis_colour(ty, NTy);
+        }
+    // colour orders: all of them (mixed uniformly) or the palindrome
+    P.n_orders = 0;
+    if (pal) {
+        P.order_len = 2 * ncol;
+        for (int k = 0; k < ncol; ++k) {
+            P.orders[0][k] = k;
+            P.orders[0][2 * ncol - 1 - k] = k;
+        }
+        P.n_orders = 1;
+    } else {
+        int o[4];
+        for (int k = 0; k < ncol; ++k) o[k] = k;
+        P.order_len = ncol;
+        do {
+            for (int k = 0; k < ncol; ++k) P.orders[P.n_orders][k] = o[k];
+            ++P.n_orders;
+        } while (std::next_permutation(o, o + ncol));
+    }
+    P.NI = d->steps_per_visit ? d->steps_per_visit : Bx * By;
+    P.inv_nd = 1.0 / (double)(Bx * By);
+    return KMC_OK;
+}
+
+// Enqueues n_sweeps sweeps of the plan on st: p in and out, work holds three
+// vectors of 2^N doubles (the mixture's accumulator and two tick buffers);
+// every entry of work is written before it is read.
+void exact_enqueue(const ExactPlan &P, int N, double *p, double *work, int64_t n_sweeps,
+                   hipStream_t st) {
+    const int64_t n = (int64_t)1 << N;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    double *acc = work, *b0 = work + n, *b1 = work + 2 * n;
+    for (int64_t sw = 0; sw < n_sweeps; ++sw) {
+        for (int k = 0; k < P.n_orders; ++k) {
+            double *cur = b0, *nxt = b1;
+            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, p, cur, n);
+            for (int q = 0; q < P.order_len; ++q)
+                for (int i = 0; i < P.n_dom; ++i) {
+                    if (P.col[i] != P.orders[k][q]) continue;
+                    for (int t = 0; t < P.NI; ++t) {
+                        hipLaunchKernelGGL(kmcdev::k_exact_tick, dim3(grid), dim3(256), 0, st,
+                                           cur, nxt, n, P.dom[i], P.R, P.inv_nd);
+                        std::swap(cur, nxt);
+                    }
+                }
+            hipLaunchKernelGGL(kmcdev::k_exact_axpy, dim3(grid), dim3(256), 0, st, acc, cur,
+                               1.0 / (double)P.n_orders, n, k == 0 ? 1 : 0);
+        }
+        hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, acc, p, n);
+    }
+}
+
+}  // namespace
+
 extern "C" kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
                                        int64_t n_sweeps, uint32_t flags, void *hip_stream) {
     if (!d || !p || !work || n_sweeps < 0) return KMC_EINVAL;
     try {
-        validate(nullptr, *d, 0);
-        const int L = d->L, N = L * L;
-        if (N > kmcdev::kExactMaxSites) return KMC_EINVAL;
-        const int Bx = d->tile, By = tile_rows_of(*d), NTx = L / Bx, NTy = L / By;
-        const int cx = axis_colours(NTx), ncol = cx * axis_colours(NTy);
-        const bool pal = d->schedule == KMC_SCHED_PALINDROME;
-        if (!pal && ncol > 4) return KMC_EUNSUPPORTED;  // more than 4! orders to mix
-        uint64_t r[10];
-        double w[10], gJ[10], gh[10];
-        if (rate_table(d->J, d->h, d->T, d->rate_model, r, w, gJ, gh) != KMC_OK)
-            return KMC_EINVAL;
-        kmcdev::ExactRates R;
-        for (int c = 0; c < 10; ++c)
-            R.w[c] = (flags & KMC_EXACT_QUANTISED) ? (double)r[c] * 0x1p-32 : w[c];
-        // domains (row-major over the grid, sites row-major inside) by colour
-        auto axis_colour = [](int t, int n) { return n == 1 ? 0 : (n % 2 && t == n - 1) ? 2 : t % 2; };
-        std::vector<std::vector<kmcdev::ExactDomain>> by_colour(ncol);
-        for (int ty = 0; ty < NTy; ++ty)
-            for (int tx = 0; tx < NTx; ++tx) {
-                kmcdev::ExactDomain D;
-                std::memset(&D, 0, sizeof(D));
-                D.n = Bx * By;
-                for (int ly = 0; ly < By; ++ly)
-                    for (int lx = 0; lx < Bx; ++lx) {
-                        const int a = ly * Bx + lx, y = ty * By + ly, x = tx * Bx + lx;
-                        D.site[a] = y * L + x;
-                        D.nb[a][0] = ((y + L - 1) % L) * L + x;
-                        D.nb[a][1] = ((y + 1) % L) * L + x;
-                        D.nb[a][2] = y * L + (x + L - 1) % L;
-                        D.nb[a][3] = y * L + (x + 1) % L;
-                    }
-                by_colour[axis_colour(tx, NTx) + cx * axis_colour(ty, NTy)].push_back(D);
-            }
-        // colour orders: all of them (mixed uniformly) or the palindrome
-        std::vector<std::vector<int>> orders;
-        if (pal) {
-            std::vector<int> o;
-            for (int k = 0; k < ncol; ++k) o.push_back(k);
-            for (int k = ncol - 1; k >= 0; --k) o.push_back(k);
-            orders.push_back(o);
-        } else {
-            std::vector<int> o(ncol);
-            for (int k = 0; k < ncol; ++k) o[k] = k;
-            do orders.push_back(o); while (std::next_permutation(o.begin(), o.end()));
-        }
-        const int NI = d->steps_per_visit ? d->steps_per_visit : Bx * By;
-        const int64_t n = (int64_t)1 << N;
-        hipStream_t st = (hipStream_t)hip_stream;
-        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-        double *acc = work, *b0 = work + n, *b1 = work + 2 * n;
-        const double inv_nd = 1.0 / (double)(Bx * By);
-        auto run_order = [&](const std::vector<int> &o, const double *src) -> double * {
-            double *cur = b0, *nxt = b1;
-            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, src, cur, n);
-            for (int col : o)
-                for (const kmcdev::ExactDomain &D : by_colour[col])
-                    for (int t = 0; t < NI; ++t) {
-                        hipLaunchKernelGGL(kmcdev::k_exact_tick, dim3(grid), dim3(256), 0, st,
-                                           cur, nxt, n, D, R, inv_nd);
-                        std::swap(cur, nxt);
-                    }
-            return cur;
-        };
-        for (int64_t sw = 0; sw < n_sweeps; ++sw) {
-            for (size_t k = 0; k < orders.size(); ++k) {
-                const double *res = run_order(orders[k], p);
-                hipLaunchKernelGGL(kmcdev::k_exact_axpy, dim3(grid), dim3(256), 0, st, acc, res,
-                                   1.0 / (double)orders.size(), n, k == 0 ? 1 : 0);
-            }
-            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, acc, p, n);
-        }
+        ExactPlan P;
+        const kmc_status st = exact_plan(d, flags, kmcdev::kExactMaxSites, P);
+        if (st != KMC_OK) return st;
+        exact_enqueue(P, d->L * d->L, p, work, n_sweeps, (hipStream_t)hip_stream);
+        if (hipGetLastError() != hipSuccess) return KMC_EDEVICE;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+    return KMC_OK;
+}
+
+// ------------------------------------------- exact propagation, no allocation
+//
+// The work vectors of kmc_exact_sweeps_static live in this file-scope device
+// array: 3 * 2^16 doubles (1.5 MiB), held by every device the library runs
+// on until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): its device
+// address is taken once per device with hipGetSymbolAddress, with that
+// device current, and kept here.
+constexpr int kExactStaticMaxSites = 16;
+static __device__ __align__(256) double scratch[3 * ((size_t)1 << kExactStaticMaxSites)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up on the
+// first call there).
+kmc_status scratch_address(double **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KMC_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return KMC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return KMC_EDEVICE;
+        g_scratch[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return KMC_OK;
+}
+
+}  // namespace
+
+extern "C" kmc_status kmc_exact_sweeps_static(const kmc_replica_desc *d, double *p,
+                                              int64_t n_sweeps, uint32_t flags,
+                                              void *hip_stream) {
+    if (!d || !p || n_sweeps < 0) return KMC_EINVAL;
+    try {
+        ExactPlan P;
+        const kmc_status st = exact_plan(d, flags, kExactStaticMaxSites, P);
+        if (st != KMC_OK) return st;
+        double *work = nullptr;
+        const kmc_status sa = scratch_address(&work);
+        if (sa != KMC_OK) return sa;
+        exact_enqueue(P, d->L * d->L, p, work, n_sweeps, (hipStream_t)hip_stream);
         if (hipGetLastError() != hipSuccess) return KMC_EDEVICE;
     } catch (const Fail &f) {
         return f.st;

@@ -75,6 +75,7 @@ def lib():
             "kmc_get_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], I32),
             "kmc_get_timing": ([P, C.POINTER(C.c_double), C.POINTER(I64)], I32),
             "kmc_exact_sweeps": ([C.POINTER(ReplicaDesc), P, P, I64, C.c_uint32, P], I32),
+            "kmc_exact_sweeps_static": ([C.POINTER(ReplicaDesc), P, I64, C.c_uint32, P], I32),
             "kmc_set_wait_limit": ([P, I64], I32),
             "kmc_last_error": ([P], C.c_char_p),
             "kmc_destroy": ([P], None),
@@ -94,7 +95,8 @@ def exported_symbols():
              "kmc_run_schedule", "kmc_observables", "kmc_backward_score", "kmc_get_spins",
              "kmc_get_domain_state", "kmc_get_domain_clocks", "kmc_get_info",
              "kmc_get_timing", "kmc_last_error",
-             "kmc_destroy", "kmc_exact_sweeps", "kmc_set_wait_limit"]
+             "kmc_destroy", "kmc_exact_sweeps", "kmc_exact_sweeps_static",
+             "kmc_set_wait_limit"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -168,6 +170,22 @@ def kmc_exact_sweeps(desc, p, work, n_sweeps, quantised=True, stream=None):
     _check(lib().kmc_exact_sweeps(arr, C.c_void_p(p.data_ptr()), C.c_void_p(work.data_ptr()),
                                   int(n_sweeps), EXACT_QUANTISED if quantised else 0,
                                   C.c_void_p(stream) if stream else None))
+
+
+def kmc_exact_sweeps_static(desc, p, n_sweeps, quantised=True, stream=None):
+    """kmc_exact_sweeps without a workspace (the library's own buffer; at
+    most 16 sites): p is a float64 CUDA tensor of 2^(L*L) entries, updated in
+    place on torch's current stream."""
+    import torch
+    n = 1 << (int(desc["L"]) ** 2)
+    if not (p.is_cuda and p.dtype == torch.float64 and p.is_contiguous() and p.numel() >= n):
+        raise ValueError("p must be a contiguous float64 CUDA tensor of 2^N entries")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    arr = make_descs([desc])
+    _check(lib().kmc_exact_sweeps_static(arr, C.c_void_p(p.data_ptr()), int(n_sweeps),
+                                         EXACT_QUANTISED if quantised else 0,
+                                         C.c_void_p(stream) if stream else None))
 
 
 def kmc_init_lattice(descs, seed, given_spins=None, stream=None):

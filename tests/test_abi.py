@@ -112,6 +112,14 @@ def test_exact_sweeps_rejects_bad_arguments(kmc):
     ok = kmc.make_descs([dict(L=4, tile=2, T=2.0)])
     assert L.kmc_exact_sweeps(ok, None, p, 1, 0, None) == kmc.KMC_EINVAL
     assert L.kmc_exact_sweeps(ok, p, p, -1, 0, None) == kmc.KMC_EINVAL
+    # the allocation-free form holds at most 16 sites in its own buffer
+    five = kmc.make_descs([dict(L=5, tile=5, T=2.0)])         # 25 sites > 16
+    assert L.kmc_exact_sweeps_static(five, p, 1, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_exact_sweeps_static(big, p, 1, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_exact_sweeps_static(bad, p, 1, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_exact_sweeps_static(nine, p, 1, 0, None) == kmc.KMC_EUNSUPPORTED
+    assert L.kmc_exact_sweeps_static(ok, None, 1, 0, None) == kmc.KMC_EINVAL
+    assert L.kmc_exact_sweeps_static(ok, p, -1, 0, None) == kmc.KMC_EINVAL
     L.kmc_destroy(None)
 
 
