@@ -80,6 +80,15 @@ def traffic_per_sweep(workload):
     return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
 
 
+def ticks_per_sweep(d):
+    """Site updates (ticks, nulls included) of one sweep of a replica: N_I
+    per domain visit."""
+    bx = d["tile"]
+    by = d.get("tile_rows") or bx
+    visits = 2 if d.get("schedule") == 1 else 1
+    return (d["L"] // bx) * (d["L"] // by) * (d.get("steps_per_visit") or bx * by) * visits
+
+
 def alg_bytes_per_sweep(d):
     """Algorithmic HBM bytes of one sweep of a plain lattice: every visit
     reads its int8 tile and the 2 (Bx + By) halo sites and writes the tile
@@ -128,8 +137,7 @@ def plain(args, kmc, desc, seed, steps, warmup, phased=False, graph=False):
     kernel_ms, launches = (lat.timing() if not graph
                            else (None, (4 if phased else 1) * steps))
     events = int(lat.records()[0][-1]["events"]) - ev0
-    nd = (d["L"] // d["tile"]) ** 2
-    ticks = steps * nd * d["steps_per_visit"]
+    ticks = steps * ticks_per_sweep(d)
     lat.close()
     kernel_sec = kernel_ms / 1e3 if kernel_ms is not None else sec
     kern = ("k_phase" if phased else "k_flow") + (
@@ -188,7 +196,7 @@ def batched(args, kmc, workloads):
     sec = timed(lambda: lat.run(args.batched_sweeps, args.batched_sweeps, flags), stream)
     kernel_ms, launches = lat.timing()
     events = int(lat.records()["events"][:, -1].sum()) - ev0
-    ticks = args.batched_sweeps * sum(x["L"] ** 2 for x in descs)
+    ticks = args.batched_sweeps * sum(ticks_per_sweep(x) for x in descs)
     lat.close()
     return dict(sec=sec, ticks=ticks, events=events, replicas=len(descs),
                 sweeps=args.batched_sweeps, kernel_sec=kernel_ms / 1e3, launches=launches)
@@ -207,7 +215,7 @@ def backward(args, kmc, workloads):
     # the fused form: the forward accumulates the score as it runs
     fused = timed(lambda: lat.run(n, 10, kmc.F_PERSISTENT | kmc.F_SCORE), stream)
     fused_bwd = timed(lambda: lat.score(n // 10, out), stream)
-    ticks = n * sum(x["L"] ** 2 for x in descs)
+    ticks = n * sum(ticks_per_sweep(x) for x in descs)
     lat.close()
     return dict(fwd=fwd, bwd=bwd, ticks=ticks, overhead=(fwd + bwd) / fwd - 1.0,
                 fused=fused + fused_bwd, fused_overhead=(fused + fused_bwd) / fwd - 1.0,
@@ -289,7 +297,8 @@ def _cpu_batched_worker(job):
         d = descs[rho]
         mine.append((kmco.Replica(d["L"], d["tile"], J=d["J"], h=d["h"], T=d["T"],
                                   steps_per_visit=d["steps_per_visit"], seed=seed,
-                                  replica=rho), d["L"] ** 2))
+                                  replica=rho, tile_rows=d.get("tile_rows", 0)),
+                     ticks_per_sweep(d)))
     ticks, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
         for o, per_sweep in mine:

@@ -125,6 +125,16 @@ typedef struct {
     int32_t schedule;          /* KMC_SCHED_*                               */
     int32_t init;              /* KMC_INIT_*                                */
     int32_t tile_rows;         /* domain height By; 0 means By = Bx         */
+    int32_t dims;              /* 0 or 2: the periodic L x L lattice; 1: the
+                                  periodic ring of L sites (the paper's 1D
+                                  system, Sec. 3.1, Eq. (1D partitions)),
+                                  cut into L / tile domains of `tile`
+                                  consecutive sites (1 <= tile <= 64,
+                                  tile_rows 0 or 1); a site's class counts
+                                  its up neighbours among left and right and
+                                  dE = 2 s (J (2k - 2) + h).  Rings run in
+                                  the phase, dataflow and persistent forms
+                                  (the resident form: KMC_EUNSUPPORTED)     */
 } kmc_replica_desc;
 
 /* Observables at a sweep endpoint, the only points where statistics are
@@ -204,9 +214,9 @@ kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_model,
  *   seed        64-bit key of the counter-based generator; every random
  *               number is Philox4x32-10(key = seed, counter = (tick,
  *               domain | visit<<20 | stream<<24, sweep, replica))
- *   given_spins host int8 array with sum over replicas of L*L values,
- *               replicas concatenated in order; read only for replicas whose
- *               init is KMC_INIT_GIVEN, may be NULL otherwise
+ *   given_spins host int8 array with sum over replicas of L*L values (L for
+ *               a ring), replicas concatenated in order; read only for
+ *               replicas whose init is KMC_INIT_GIVEN, may be NULL otherwise
  *   hip_stream  hipStream_t for all work of this context; NULL = null stream
  * Validation failures return KMC_EINVAL and create nothing; *out is set only
  * on success.  Synchronises the stream before returning. */
@@ -259,7 +269,8 @@ kmc_status kmc_observables(kmc_ctx *c, kmc_record *out, int64_t capacity,
 kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capacity,
                               uint32_t flags);
 
-/* Copies replica `replica`'s lattice (L*L int8, row-major) to host memory.
+/* Copies replica `replica`'s lattice (L*L int8, row-major; L for a ring) to
+ * host memory.
  * Synchronises; KMC_EDEVICE when a dataflow wait of an earlier run gave up. */
 kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out);
 

@@ -39,11 +39,19 @@ def ensemble_sem2(A):
     return A.var(axis=0, ddof=1) / A.shape[0]
 
 
-def autocorrelation(A, max_lag):
+def autocorrelation(A, max_lag, center="trajectory"):
     """Connected autocorrelation C(k) = <dA(i) dA(i + k)> for k = 0..max_lag
-    samples, per trajectory (rows of A), averaged over trajectories."""
+    samples, per trajectory (rows of A), averaged over trajectories.  dA is A
+    minus each trajectory's own mean (center="trajectory"), or minus the mean
+    over every trajectory and sample (center="ensemble"): the paper's
+    C_A = <A(s) A(s + ds)> - <A>^2.  The trajectory mean of a window W
+    samples long lowers C by about 2 tau / W of C(0), which shortens the
+    fitted tau when W is only ten or twenty tau; the ensemble mean does not."""
     A = np.asarray(A, float)
-    dA = A - A.mean(axis=1, keepdims=True)
+    if center == "ensemble":
+        dA = A - A.mean()
+    else:
+        dA = A - A.mean(axis=1, keepdims=True)
     n = A.shape[1]
     max_lag = min(max_lag, n - 1)
     C = np.empty(max_lag + 1)
@@ -106,10 +114,11 @@ def circle_initial_condition(L):
     return np.where((y - c) ** 2 + (x - c) ** 2 <= r * r, 1, -1).astype(np.int8)
 
 
-def observable(records, L, J=1.0, h=0.0, kind="H"):
+def observable(records, L, J=1.0, h=0.0, kind="H", n_sites=None):
     """A(s) of every trajectory from records [replica, record]: the energy
-    per site H/N_S (kind "H", the paper's 2D choice) or H m (kind "Hm")."""
-    N = float(L * L)
+    per site H/N_S (kind "H", the paper's 2D choice) or H m (kind "Hm", its
+    1D choice).  N_S = L^2 unless n_sites is given (L on the ring)."""
+    N = float(n_sites or L * L)
     H = (-J * records["B"] - h * records["M"]) / N
     if kind == "H":
         return H
@@ -138,9 +147,18 @@ def run_setting(kmc, L, tile, steps_per_visit, T, n_traj, n_sweeps, record_every
 
 
 def start_record(spins, n_traj, dtype):
-    """Record of a start configuration: M and the right/down bond sum B."""
+    """Record of a start configuration: M and the right/down bond sum B (the
+    right bonds only on a ring, a 1D array of spins)."""
     s = np.asarray(spins).astype(np.int64)
     rec = np.zeros((n_traj, 1), dtype)
     rec["M"] = int(s.sum())
-    rec["B"] = int((s * np.roll(s, -1, 1)).sum() + (s * np.roll(s, -1, 0)).sum())
+    if s.ndim == 1:
+        rec["B"] = int((s * np.roll(s, -1)).sum())
+    else:
+        rec["B"] = int((s * np.roll(s, -1, 1)).sum() + (s * np.roll(s, -1, 0)).sum())
     return rec
+
+
+def start_records(starts, dtype):
+    """Start records of trajectories with different start configurations."""
+    return np.concatenate([start_record(s, 1, dtype) for s in starts], axis=0)

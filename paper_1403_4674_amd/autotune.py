@@ -1,13 +1,30 @@
-"""Tile autotuner for batched runs.
+"""Autotuner of the domain partition and the steps per domain for batched runs.
 
-The domain side B of every lattice side L in a batch is chosen by timing
-the real batch: coordinate descent over L, trying each valid B (B % 4 == 0,
-L/B even, B <= max_tile) with the other sides fixed, keeping the fastest in
-site-updates/s of the persistent kernel.  The choice changes the dynamics
-(the paper's T_PAR depends on the partition) but not the equilibrium, which
-Eq. (general reversibility condition) guarantees for any partition; the
-chosen tile is written into the descriptors, so every run and its oracle
-replay use the same partition.  Choices persist as JSON keyed by workload.
+For every lattice side L in a batch it chooses the domain shape Bx x By
+(square or rectangular, each side dividing L into an even number of domains,
+so the domain grid is a 4-colour checkerboard) and the number of ticks per
+domain visit N_I, by timing the real batch in the persistent form.
+
+Both choices change the dynamics (the paper's T_PAR depends on the partition
+and on N_I) but not the equilibrium, which Eq. (general reversibility
+condition) guarantees for any partition and any N_I; the chosen values are
+written into the descriptors, so every run and its oracle replay use the same
+partition and visit length.
+
+N_I is searched as a fraction nu = N_I / (Bx By) of a Monte Carlo step per
+site and visit, up to a cap nu_max (default 1, the benchmark workloads'
+N_I = Bx By): longer visits amortise the staging of a visit over more ticks,
+so the cap is the caller's bound on how far the decomposed dynamics may lag
+the serial ones (the paper's efficiency falls as N_I grows, Sec. 3.3).  The
+candidates are nu in {1/4, 1/2, 1} times the domain size, and each of them
+rounded to whole batches of the kernel that runs the domain (16 ticks per
+batch in the four-domains-per-wavefront kernel, 64 otherwise), within the
+cap.
+
+Search: coordinate descent over L, first over shapes at N_I = nu_max Bx By,
+then over N_I for the chosen shape, each move timed as site-updates (ticks)
+per second of the persistent kernel; the best of several starting points.
+Choices persist as JSON keyed by workload, with every trial.
 """
 import json
 import os
@@ -16,21 +33,63 @@ import time
 from . import kmc
 
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
+NUS = (0.25, 0.5, 1.0)
 
 
 def valid_tiles(L, max_tile=32, min_tile=8):
+    """Domain sides B (multiples of 4) with L / B even."""
     return [B for B in range(min_tile, min(max_tile, L // 2) + 1, 4)
             if L % B == 0 and (L // B) % 2 == 0]
 
 
+def valid_shapes(L, max_side=32, min_side=4, max_aspect=2):
+    """(Bx, By): squares of valid_tiles, and rectangles of two valid sides
+    whose aspect ratio is at most max_aspect."""
+    sides = valid_tiles(L, max_side, min_side)
+    out = [(B, B) for B in sides]
+    out += [(bx, by) for bx in sides for by in sides
+            if bx != by and max(bx, by) <= max_aspect * min(bx, by)]
+    return out
+
+
+def batch_width(bx, by):
+    """Ticks per batch of the kernel that runs such domains in the persistent
+    form: 16 in the four-domains-per-wavefront kernel (square, side <= 16),
+    64 otherwise."""
+    return 16 if bx == by and bx <= 16 else 64
+
+
+def visit_lengths(bx, by, nus=NUS, nu_max=1.0):
+    """Candidate N_I for a domain of bx x by sites (sorted, within the cap)."""
+    nd = bx * by
+    cap = int(nu_max * nd)
+    base = {max(1, int(round(nu * nd))) for nu in nus if nu <= nu_max}
+    w = batch_width(bx, by)
+    out = set(base)
+    for ni in base:
+        for v in (ni // w * w, -(-ni // w) * w):
+            if 1 <= v <= cap:
+                out.add(v)
+    return sorted(v for v in out if 1 <= v <= cap)
+
+
+def ticks_per_sweep(d):
+    bx = d["tile"]
+    by = d.get("tile_rows") or bx
+    nd = (d["L"] // bx) * (d["L"] // by)
+    visits = 2 if d.get("schedule") == kmc.SCHED_PALINDROME else 1
+    return nd * (d.get("steps_per_visit") or bx * by) * visits
+
+
 def _rate(descs, seed, sweeps, warmup=4, repeats=2):
-    """Site-updates/s of the persistent kernel on the batch: `warmup` sweeps
-    first (the random start relaxes fastest and has the most events), then
-    the best of `repeats` timed runs of `sweeps` sweeps."""
+    """Site-updates (ticks) per second of the persistent kernel on the batch:
+    `warmup` sweeps first (the random start relaxes fastest and has the most
+    events), then the best of `repeats` timed runs of `sweeps` sweeps."""
     import torch
     stream = torch.cuda.current_stream()
     lat = kmc.Lattice(descs, seed)
     lat.run(warmup, warmup, kmc.F_PERSISTENT)
+    ticks = sweeps * sum(ticks_per_sweep(d) for d in descs)
     best = 0.0
     for _ in range(repeats):
         torch.cuda.synchronize()
@@ -40,59 +99,87 @@ def _rate(descs, seed, sweeps, warmup=4, repeats=2):
         lat.run(sweeps, sweeps, kmc.F_PERSISTENT)
         b.record(stream)
         torch.cuda.synchronize()
-        best = max(best, sweeps * sum(d["L"] ** 2 for d in descs) / (a.elapsed_time(b) / 1e3))
+        best = max(best, ticks / (a.elapsed_time(b) / 1e3))
     lat.close()
     return best
 
 
-def tune_batch(name, descs, seed, sweeps=30, max_tile=32, passes=1, path=DEFAULT_PATH,
-               verbose=False, starts=None):
-    """Chooses a tile per lattice side for the batch `descs` (dicts with L,
-    tile, ...), records the choice under `name` and returns {L: tile}.
+def apply(descs, shapes):
+    """The descriptors with each lattice side's (Bx, By, N_I)."""
+    out = []
+    for d in descs:
+        bx, by, ni = shapes[int(d["L"])]
+        out.append(dict(d, tile=bx, tile_rows=by if by != bx else 0, steps_per_visit=ni))
+    return out
 
-    Coordinate descent from the best of several starting points: the
-    descriptors' tiles, the largest valid tiles up to 16 (the range of the
-    four-domains-per-wavefront kernel, which only pays once most replicas
-    use it, so single-coordinate moves from large tiles never reach it), and
-    any `starts` given."""
+
+def tune_batch(name, descs, seed, sweeps=30, max_side=32, nus=NUS, nu_max=1.0,
+               path=DEFAULT_PATH, verbose=False, starts=None):
+    """Chooses (Bx, By, N_I) per lattice side for the batch `descs` (dicts with
+    L, tile, ...), records the choice under `name` and returns
+    {L: (Bx, By, N_I)}."""
     Ls = sorted({int(d["L"]) for d in descs})
-    with_tiles = lambda tl: [dict(d, tile=tl[int(d["L"])]) for d in descs]
-    cands = [{L: int(next(d["tile"] for d in descs if d["L"] == L)) for L in Ls}]
-    small = {L: max(valid_tiles(L, 16, 4)) for L in Ls}
-    if small not in cands:
+    full = lambda bx, by: int(nu_max * bx * by)
+    trials = []
+
+    def rate(shapes, what):
+        r = _rate(apply(descs, shapes), seed, sweeps)
+        trials.append({"shapes": {str(L): list(v) for L, v in shapes.items()},
+                       "site_updates_per_s": r})
+        if verbose:
+            print(f"[autotune] {name} {what}: {r:.3e} site-updates/s", flush=True)
+        return r
+
+    # starting points: the descriptors' own tiles, the largest square sides
+    # up to 16 (the four-domains-per-wavefront kernel only pays once most
+    # replicas use it, so single-coordinate moves from large sides never
+    # reach it), and any given
+    first = {}
+    for L in Ls:
+        d = next(x for x in descs if x["L"] == L)
+        bx = int(d["tile"])
+        by = int(d.get("tile_rows") or bx)
+        first[L] = (bx, by, full(bx, by))
+    cands = [first]
+    small = {}
+    for L in Ls:
+        B = max(valid_tiles(L, 16, 4))
+        small[L] = (B, B, full(B, B))
+    if small != first:
         cands.append(small)
     cands += [dict(s) for s in (starts or []) if s not in cands]
-    trials = []
-    best, tiles = -1.0, None
+    best, shapes = -1.0, None
     for c in cands:
-        r = _rate(with_tiles(c), seed, sweeps)
-        trials.append({"tiles": dict(c), "site_updates_per_s": r})
-        if verbose:
-            print(f"[autotune] {name} start {c}: {r:.3e} site-updates/s", flush=True)
+        r = rate(c, f"start {c}")
         if r > best:
-            best, tiles = r, dict(c)
-    for _ in range(passes):
-        for L in Ls:
-            for B in valid_tiles(L, max_tile):
-                if B == tiles[L]:
-                    continue
-                cand = dict(tiles)
-                cand[L] = B
-                r = _rate(with_tiles(cand), seed, sweeps)
-                trials.append({"tiles": dict(cand), "site_updates_per_s": r})
-                if verbose:
-                    print(f"[autotune] {name} L={L} B={B}: {r:.3e} site-updates/s", flush=True)
-                if r > best:
-                    best, tiles = r, cand
+            best, shapes = r, dict(c)
+    # 1) shapes, at the capped visit length
+    for L in Ls:
+        for bx, by in valid_shapes(L, max_side):
+            cand = dict(shapes)
+            cand[L] = (bx, by, full(bx, by))
+            if cand[L] == shapes[L]:
+                continue
+            r = rate(cand, f"L={L} {bx}x{by}")
+            if r > best:
+                best, shapes = r, cand
+    # 2) visit lengths of the chosen shapes
+    for L in Ls:
+        bx, by, _ = shapes[L]
+        for ni in visit_lengths(bx, by, nus, nu_max):
+            cand = dict(shapes)
+            cand[L] = (bx, by, ni)
+            if cand[L] == shapes[L]:
+                continue
+            r = rate(cand, f"L={L} {bx}x{by} N_I={ni}")
+            if r > best:
+                best, shapes = r, cand
     table = load(path)
-    table[name] = {"tiles": {str(k): v for k, v in tiles.items()},
-                   "site_updates_per_s": best, "sweeps": sweeps,
-                   "trials": [{"tiles": {str(k): v for k, v in t["tiles"].items()},
-                               "site_updates_per_s": t["site_updates_per_s"]}
-                              for t in trials],
-                   "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    table[name] = {"shapes": {str(L): list(v) for L, v in shapes.items()},
+                   "site_updates_per_s": best, "sweeps": sweeps, "nu_max": nu_max,
+                   "trials": trials, "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
     save(table, path)
-    return tiles
+    return shapes
 
 
 def load(path=DEFAULT_PATH):
@@ -109,12 +196,12 @@ def save(table, path=DEFAULT_PATH):
     os.replace(tmp, path)
 
 
-def tiles_for(name, path=DEFAULT_PATH):
-    """The tuned {L: tile} of workload `name`, or None."""
+def shapes_for(name, path=DEFAULT_PATH):
+    """The tuned {L: (Bx, By, N_I)} of workload `name`, or None."""
     entry = load(path).get(name)
-    if not entry:
+    if not entry or "shapes" not in entry:
         return None
-    return {int(k): int(v) for k, v in entry["tiles"].items()}
+    return {int(k): tuple(int(x) for x in v) for k, v in entry["shapes"].items()}
 
 
 def main():
@@ -128,17 +215,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--sweeps", type=int, default=30)
+    ap.add_argument("--nu-max", type=float, default=1.0)
     args = ap.parse_args()
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
     DEF = workloads.DEFAULT_TILE
-    seed, descs, _ = workloads.batched_4096(tiles=DEF)
+    seed, descs, _ = workloads.batched_4096(shapes={L: (B, B, B * B) for L, B in DEF.items()})
     print("batched_4096", tune_batch("batched_4096", descs, seed, sweeps=args.sweeps,
-                                     path=args.out, verbose=True), flush=True)
-    seed, descs, _ = workloads.differentiable_1024(tile=32)
+                                     nu_max=args.nu_max, path=args.out, verbose=True),
+          flush=True)
+    seed, descs, _ = workloads.differentiable_1024(shape=(32, 32, 1024))
     print("differentiable_1024", tune_batch("differentiable_1024", descs, seed,
-                                            sweeps=args.sweeps, path=args.out,
-                                            verbose=True), flush=True)
+                                            sweeps=args.sweeps, nu_max=args.nu_max,
+                                            path=args.out, verbose=True), flush=True)
 
 
 if __name__ == "__main__":

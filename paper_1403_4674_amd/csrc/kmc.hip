@@ -182,16 +182,18 @@ void fail(kmc_ctx *c, kmc_status st, const std::string &msg) {
     throw Fail{st};
 }
 
-// Per-class rates (Appendix A, Eq. (Glauber_TM)); classes c = 5*[s=+1] + k.
+// Per-class rates (Appendix A, Eq. (Glauber_TM)); classes c = 5*[s=+1] + k
+// with k the up neighbours among z (4 on the square lattice, 2 on the ring;
+// classes with k > z stay empty).
 kmc_status rate_table(double J, double h, double T, int32_t model, uint64_t r[10],
-                      double w[10], double gJ[10], double gh[10]) {
+                      double w[10], double gJ[10], double gh[10], int z = 4) {
     if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(J) || !std::isfinite(h))
         return KMC_EINVAL;
     if (model != KMC_RATE_METROPOLIS && model != KMC_RATE_BARKER) return KMC_EINVAL;
     for (int c = 0; c < 10; ++c) {
         const int up = c / 5, k = c % 5;
         const double s = up ? 1.0 : -1.0;
-        const double n = (double)(2 * k - 4);
+        const double n = (double)(2 * k - z);
         const double dE = 2.0 * s * (J * n + h);
         double wc, dlw;  // w and d ln w / d dE
         if (model == KMC_RATE_METROPOLIS) {
@@ -236,8 +238,16 @@ double sweep_cost(const Rep &rp, const kmc_replica_desc &d) {
     return (double)rp.NI * rp.ND * rp.visits * (1.0 + 6.0 * p);
 }
 
-// Domain height By (tile_rows 0: square domains).
-int tile_rows_of(const kmc_replica_desc &d) { return d.tile_rows ? d.tile_rows : d.tile; }
+// The periodic ring of L sites (the paper's 1D system), one row.
+bool is_ring(const kmc_replica_desc &d) { return d.dims == 1; }
+
+// Domain height By (tile_rows 0: square domains; 1 on the ring).
+int tile_rows_of(const kmc_replica_desc &d) {
+    return is_ring(d) ? 1 : (d.tile_rows ? d.tile_rows : d.tile);
+}
+
+// Rows of the lattice: L, or 1 on the ring.
+int rows_of(const kmc_replica_desc &d) { return is_ring(d) ? 1 : d.L; }
 
 // Colours along an axis of n domains (1, 2 for an even count, 3 for odd),
 // and the most domains any one colour holds on it.
@@ -250,7 +260,8 @@ int max_per_colour(const Rep &rp) { return axis_most(rp.NT) * axis_most(rp.NTy);
 // Replicas the multi-slot kernel runs: square domains of at most 16 x 16 on a
 // 4-colour checkerboard.
 bool multi_ok(const Rep &rp) {
-    return rp.B <= 16 && rp.By == rp.B && rp.NT >= 2 && rp.NT % 2 == 0 && rp.NTy == rp.NT;
+    return rp.z == 4 && rp.B <= 16 && rp.By == rp.B && rp.NT >= 2 && rp.NT % 2 == 0 &&
+           rp.NTy == rp.NT;
 }
 
 // Row masks of 64 bits (and 64-lane row scans) when a domain is wider or
@@ -262,7 +273,7 @@ bool big(const Rep &rp) { return rp.B > 64 || rp.By > 64; }
 
 // Replicas the resident form can hold in one workgroup's LDS.
 bool resident_ok(const Rep &rp) {
-    return rp.L >= 3 && rp.L <= kmcdev::kResMaxL && rp.NT <= kmcdev::kResMaxNTx;
+    return rp.z == 4 && rp.L >= 3 && rp.L <= kmcdev::kResMaxL && rp.NT <= kmcdev::kResMaxNTx;
 }
 
 void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
@@ -271,20 +282,30 @@ void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     };
     if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
         bad("J, h must be finite and T > 0");
+    if (d.dims != 0 && d.dims != 1 && d.dims != 2) bad("dims must be 0, 1 or 2");
+    if (is_ring(d)) {
+        if (d.tile_rows != 0 && d.tile_rows != 1) bad("a ring's tile_rows must be 0 or 1");
+        if (d.tile < 1 || d.tile > 64) bad("a ring's tile must be in [1, 64]");
+        if (d.L < d.tile || d.L % d.tile) bad("L must be a multiple of tile");
+        if (d.L == d.tile && d.tile < 3)
+            bad("a domain as long as the ring needs tile >= 3 (distinct left and right "
+                "neighbours)");
+        if (d.L / d.tile > (1 << 20)) bad("more than 2^20 domains");
+    }
     const int by = tile_rows_of(d);
     if (d.tile < 1 || d.tile > 128) bad("tile must be in [1, 128]");
     if (by < 1 || by > 128) bad("tile_rows must be 0 or in [1, 128]");
     if ((d.tile > 64 || by > 64) && d.L > kmcdev::kResMaxL)
         bad("domains over 64 sites a side need L <= 128 (resident form)");
     if (d.L < d.tile || d.L % d.tile) bad("L must be a multiple of tile");
-    if (d.L < by || d.L % by) bad("L must be a multiple of tile_rows");
+    if (rows_of(d) < by || rows_of(d) % by) bad("L must be a multiple of tile_rows");
     if (d.L == d.tile && d.tile < 3)
         bad("a domain as wide as the lattice needs tile >= 3 (distinct left and right "
             "neighbours)");
-    if (d.L == by && by < 3)
+    if (!is_ring(d) && d.L == by && by < 3)
         bad("a domain as high as the lattice needs tile_rows >= 3 (distinct up and down "
             "neighbours)");
-    if ((int64_t)(d.L / d.tile) * (d.L / by) > (1 << 20)) bad("more than 2^20 domains");
+    if ((int64_t)(d.L / d.tile) * (rows_of(d) / by) > (1 << 20)) bad("more than 2^20 domains");
     if (d.steps_per_visit < 0) bad("steps_per_visit must be >= 0");
     if (d.rate_model != KMC_RATE_METROPOLIS && d.rate_model != KMC_RATE_BARKER)
         bad("unknown rate model");
@@ -621,7 +642,7 @@ void run_persistent_graph(kmc_ctx *c, KParams K, int64_t n_sweeps, int32_t recor
     if (i < n_sweeps) launch_persistent<false>(c, K, n_sweeps - i, flags);
 }
 
-int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * d.L; }
+int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * rows_of(d); }
 
 // A one-launch sweep whose bounded wait gave up leaves ctl->err set (a
 // dependency never satisfied): the results of the run are not valid.
@@ -691,15 +712,17 @@ struct ExactPlan {
 // Validates d and fills the plan; KMC_OK, KMC_EINVAL or KMC_EUNSUPPORTED.
 kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, ExactPlan &P) {
     validate(nullptr, *d, 0);  // throws Fail{KMC_EINVAL}
-    const int L = d->L, N = L * L;
+    const bool ring = is_ring(*d);
+    const int L = d->L, Ly = rows_of(*d), N = L * Ly;
     if (N > max_sites) return KMC_EINVAL;
-    const int Bx = d->tile, By = tile_rows_of(*d), NTx = L / Bx, NTy = L / By;
+    const int Bx = d->tile, By = tile_rows_of(*d), NTx = L / Bx, NTy = Ly / By;
     const int cx = axis_colours(NTx), ncol = cx * axis_colours(NTy);
     const bool pal = d->schedule == KMC_SCHED_PALINDROME;
     if (!pal && ncol > 4) return KMC_EUNSUPPORTED;  // more than 4! orders to mix
     uint64_t r[10];
     double w[10], gJ[10], gh[10];
-    if (rate_table(d->J, d->h, d->T, d->rate_model, r, w, gJ, gh) != KMC_OK) return KMC_EINVAL;
+    if (rate_table(d->J, d->h, d->T, d->rate_model, r, w, gJ, gh, ring ? 2 : 4) != KMC_OK)
+        return KMC_EINVAL;
     for (int c = 0; c < 10; ++c)
         P.R.w[c] = (flags & KMC_EXACT_QUANTISED) ? (double)r[c] * 0x1p-32 : w[c];
     // domains (row-major over the grid, sites row-major inside)
@@ -714,8 +737,10 @@ kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, 
                 for (int lx = 0; lx < Bx; ++lx) {
                     const int a = ly * Bx + lx, y = ty * By + ly, x = tx * Bx + lx;
                     D.site[a] = y * L + x;
-                    D.nb[a][0] = ((y + L - 1) % L) * L + x;
-                    D.nb[a][1] = ((y + 1) % L) * L + x;
+                    // on the ring the up and down neighbours are bit N of the
+                    // state index, which is 0 for every state: never up
+                    D.nb[a][0] = ring ? N : ((y + L - 1) % L) * L + x;
+                    D.nb[a][1] = ring ? N : ((y + 1) % L) * L + x;
                     D.nb[a][2] = y * L + (x + L - 1) % L;
                     D.nb[a][3] = y * L + (x + 1) % L;
                 }
@@ -781,7 +806,7 @@ extern "C" kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, dou
         ExactPlan P;
         const kmc_status st = exact_plan(d, flags, kmcdev::kExactMaxSites, P);
         if (st != KMC_OK) return st;
-        exact_enqueue(P, d->L * d->L, p, work, n_sweeps, (hipStream_t)hip_stream);
+        exact_enqueue(P, d->L * rows_of(*d), p, work, n_sweeps, (hipStream_t)hip_stream);
         if (hipGetLastError() != hipSuccess) return KMC_EDEVICE;
     } catch (const Fail &f) {
         return f.st;
@@ -836,7 +861,7 @@ extern "C" kmc_status kmc_exact_sweeps_static(const kmc_replica_desc *d, double 
         double *work = nullptr;
         const kmc_status sa = scratch_address(&work);
         if (sa != KMC_OK) return sa;
-        exact_enqueue(P, d->L * d->L, p, work, n_sweeps, (hipStream_t)hip_stream);
+        exact_enqueue(P, d->L * rows_of(*d), p, work, n_sweeps, (hipStream_t)hip_stream);
         if (hipGetLastError() != hipSuccess) return KMC_EDEVICE;
     } catch (const Fail &f) {
         return f.st;
@@ -878,7 +903,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             rp.B = q.tile;
             rp.By = tile_rows_of(q);
             rp.NT = q.L / q.tile;
-            rp.NTy = q.L / rp.By;
+            rp.NTy = rows_of(q) / rp.By;
+            rp.z = is_ring(q) ? 2 : 4;
             rp.cx = axis_colours(rp.NT);
             rp.ncol = rp.cx * axis_colours(rp.NTy);
             rp.nperm = 1;
@@ -900,7 +926,7 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             Rates &R = c->rates[rho];
             std::memset(&R, 0, sizeof(R));
             double gJ[10], gh[10];
-            if (rate_table(q.J, q.h, q.T, q.rate_model, R.r, R.w, gJ, gh) != KMC_OK)
+            if (rate_table(q.J, q.h, q.T, q.rate_model, R.r, R.w, gJ, gh, rp.z) != KMC_OK)
                 fail(c, KMC_EINVAL, "replica " + std::to_string(rho) + ": rate table");
             for (int k = 0; k < 10; ++k) {
                 R.rd[k] = (double)R.r[k];
@@ -1109,6 +1135,11 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
                 fail(c, KMC_EINVAL,
                      "KMC_F_RESIDENT is not available with KMC_F_PERSISTENT, KMC_F_FLOW or "
                      "KMC_F_GRAPH");
+            for (int rho = 0; rho < c->n_rep; ++rho)
+                if (c->reps[rho].z == 2)
+                    fail(c, KMC_EUNSUPPORTED,
+                         "replica " + std::to_string(rho) +
+                             ": the resident form holds square lattices only");
             for (int rho = 0; rho < c->n_rep; ++rho)
                 if (!resident_ok(c->reps[rho]))
                     fail(c, KMC_EINVAL,
@@ -1329,7 +1360,8 @@ extern "C" kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out) {
     }
     try {
         const Rep &rp = c->reps[replica];
-        hip_check(c, hipMemcpyAsync(out, c->d_spins + rp.spin_off, (size_t)rp.L * rp.L,
+        hip_check(c, hipMemcpyAsync(out, c->d_spins + rp.spin_off,
+                                    (size_t)kmcdev::lattice_sites(rp),
                                     hipMemcpyDeviceToHost, c->stream), "spin copy");
         hip_check(c, hipStreamSynchronize(c->stream), "spin sync");
         check_flow_error(c, c->d_ctl);

@@ -66,7 +66,14 @@ struct Rep {
     int32_t task_off;       // first phase task
     int32_t visits;         // visits of each domain per sweep (1 or 2)
     int32_t init;           // kmc_init kind
+    int32_t z;              // neighbours per site: 4 (L x L lattice) or 2 (ring
+                            // of L sites: one row, By = NTy = 1)
 };
+
+// Sites of a replica's lattice: L^2, or L on the ring.
+__device__ __host__ __forceinline__ int64_t lattice_sites(const Rep &rp) {
+    return rp.z == 2 ? (int64_t)rp.L : (int64_t)rp.L * rp.L;
+}
 
 struct Dom {
     double clk_sum, clk_comp;  // compensated event clock
@@ -673,6 +680,9 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds;
     uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
+    // the ring (one row of L sites) has no rows above and below: its domains
+    // have no top and bottom halo, and those neighbours count as down
+    const bool ring = rp.z == 2;
     if ((B & 3) == 0) {
         for (int q = lane; q < By * B4; q += 64) {
             const int row = q / B4, c4 = q - row * B4;
@@ -680,7 +690,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                 lat + (int64_t)(oy + row) * L + ox + 4 * c4);
             *reinterpret_cast<uint32_t *>(tile + row * SB + 4 * c4) = v;
         }
-        if (lane < 2 * B4) {
+        if (lane < 2 * B4 && !ring) {
             const int which = lane / B4, c4 = lane - which * B4;
             const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
             const uint32_t v =
@@ -692,7 +702,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             const int row = q / B, col = q - row * B;
             tile[row * SB + col] = (uint8_t)lat[(int64_t)(oy + row) * L + ox + col];
         }
-        for (int q = lane; q < 2 * B; q += 64) {
+        for (int q = lane; q < 2 * B && !ring; q += 64) {
             const int which = q / B, col = q - which * B;
             const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
             hrow[which * 64 + col] = (uint8_t)lat[(int64_t)y * L + ox + col];
@@ -720,8 +730,8 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                << (4 * q);
     }
     S &= VM;  // padding bytes decode to set bits: clear them
-    top &= vm_row;
-    bot &= vm_row;
+    top = ring ? (MT)0 : top & vm_row;
+    bot = ring ? (MT)0 : bot & vm_row;
     Planes<MT> P = neighbour_planes<MT>(S, top, bot, hl, hr, B, By, VM, lane);
 
     // ---- class counts: per-row popcounts, two classes per 32-bit word
@@ -757,7 +767,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     // along an axis with a single domain (one domain, or a stripe) the
     // domain is periodic in itself: its boundary neighbours on that axis are
     // its own sites and change during the visit
-    const int wrapY = WRAP && rp.NTy == 1 ? By : 0;
+    const int wrapY = WRAP && rp.NTy == 1 && !ring ? By : 0;
     const int wrapX = WRAP && rp.NT == 1 ? B : 0;
 
     // Score.  A run of m null ticks adds m d ln(1 - R_w/n_d)/d theta =
@@ -948,7 +958,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             const int64_t m2 = cc >= 5 ? -2 : 2;
             out.events += n;
             out.dM += m2 * n;
-            out.dB += m2 * (2 * (cc % 5) - 4) * n;
+            out.dB += m2 * (2 * (cc % 5) - rp.z) * n;
         }
     }
     {
@@ -1443,7 +1453,7 @@ __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
 __global__ void k_init_spins(KParams K) {
     const int rho = blockIdx.y;
     const Rep rp = K.reps[rho];
-    const int64_t N = (int64_t)rp.L * rp.L;
+    const int64_t N = lattice_sites(rp);
     const int64_t call = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (call * 128 >= N || rp.init == 2) return;
     int8_t *lat = K.spins + rp.spin_off;
@@ -1463,7 +1473,7 @@ __global__ __launch_bounds__(256) void k_init_obs(KParams K) {
     const int rho = blockIdx.y;
     const Rep rp = K.reps[rho];
     const int L = rp.L;
-    const int64_t N = (int64_t)L * L;
+    const int64_t N = lattice_sites(rp);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int m = 0, b = 0;
     if (i < N) {
@@ -1471,7 +1481,8 @@ __global__ __launch_bounds__(256) void k_init_obs(KParams K) {
         const int y = (int)(i / L), x = (int)(i % L);
         const int s = lat[i];
         m = s;
-        b = s * (lat[(int64_t)y * L + (x + 1) % L] + lat[(int64_t)((y + 1) % L) * L + x]);
+        b = s * lat[(int64_t)y * L + (x + 1) % L];  // right bond
+        if (rp.z == 4) b += s * lat[(int64_t)((y + 1) % L) * L + x];  // down bond
     }
     const uint32_t sm = wave_sum_u32((uint32_t)m);
     const uint32_t sb = wave_sum_u32((uint32_t)b);

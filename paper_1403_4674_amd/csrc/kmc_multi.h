@@ -349,7 +349,7 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
         const int64_t m2 = cc >= 5 ? -2 : 2;
         out.events += n;
         out.dM += m2 * n;
-        out.dB += m2 * (2 * (cc % 5) - 4) * n;
+        out.dB += m2 * (2 * (cc % 5) - 4) * n;  // square lattices only
     }
     {
         const double cs = sum_row_f64(clk_sum, base);

@@ -244,7 +244,7 @@ __device__ VisitOut visit_resident(const Rep &rp, const Rates *__restrict__ rt, 
         const int64_t m2 = cc >= 5 ? -2 : 2;
         out.events += n;
         out.dM += m2 * n;
-        out.dB += m2 * (2 * (cc % 5) - 4) * n;
+        out.dB += m2 * (2 * (cc % 5) - 4) * n;  // square lattices only
     }
     {
         double cs = wave_sum_f64(clk_sum), cc = wave_sum_f64(clk_comp);

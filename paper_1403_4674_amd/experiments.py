@@ -8,6 +8,7 @@ batch of independent trajectories in one persistent launch.  The analysis
 
     python -m paper_1403_4674_amd.experiments --L 12     # 500 x 1.6e5 steps
     python -m paper_1403_4674_amd.experiments --L 100    # 50 x 1.6e7 steps
+    python -m paper_1403_4674_amd.experiments --ring     # 1 x 8: 6000 x 800 steps
 
 (Table 1's trajectory counts and run lengths) prints one JSON line per
 setting and a summary line; `--save FILE.npz` also keeps every setting's
@@ -118,6 +119,109 @@ def analyse(results, L, eq_fraction=0.5, max_lag_samples=400, n_boot=30, boot_se
     return out
 
 
+# ------------------------------------------------------------------ the ring
+#
+# The paper's 1D study (Sec. 3.1, Eq. (1D partitions), Table 1): a periodic
+# ring of 8 sites at 1/(beta J) = 2 with Glauber (Barker) rates, started from
+# the eight configurations with two adjacent up spins, evolved serially
+# (N_D = 1, the reference) and with N_D in {2, 4, 8} domains for N_I in
+# {1, 2, 5, 10}; 6000 trajectories of S = 800 steps per setting.  A = H m.
+
+RING_RUN = (8, 6000, 800)  # sites, trajectories, steps (Table 1)
+
+
+def settings_ring(N=8):
+    """(label, domain length, N_I) of the reference and the partitions."""
+    out = [("reference", N, 1)]
+    for nd in (2, 4, 8):
+        if N % nd:
+            continue
+        for NI in (1, 2, 5, 10):
+            out.append((f"N_D={nd} N_I={NI}", N // nd, NI))
+    return out
+
+
+def ring_starts(N, n_traj):
+    """Trajectory k starts from the k mod N-th configuration with two
+    adjacent up spins (sites k mod N and k mod N + 1)."""
+    out = []
+    for k in range(n_traj):
+        s = -np.ones(N, np.int8)
+        s[k % N] = s[(k + 1) % N] = 1
+        out.append(s)
+    return out
+
+
+def run_ring_study(kmc, N=8, n_traj=6000, total_steps=800, T=2.0, seed=1998, verbose=True):
+    """Every ring setting for total_steps steps per trajectory, sampled at
+    every sweep end (N_D N_I steps apart), each as one persistent launch of
+    n_traj replicas; records [n_traj, samples] with the start (s = 0) first."""
+    starts = ring_starts(N, n_traj)
+    results = []
+    for k, (label, B, NI) in enumerate(settings_ring(N)):
+        nd = N // B
+        per_sweep = nd * NI
+        n_sweeps = max(1, total_steps // per_sweep)
+        d = dict(L=N, tile=B, T=T, steps_per_visit=NI, rate_model=kmc.RATE_BARKER,
+                 init=kmc.INIT_GIVEN, dims=1)
+        t0 = time.perf_counter()
+        lat = kmc.Lattice([d] * n_traj, seed + k, given_spins=starts)
+        lat.run(n_sweeps, 1, kmc.F_PERSISTENT)
+        rec = lat.records()
+        lat.close()
+        sec = time.perf_counter() - t0
+        rec = np.concatenate([analysis.start_records(starts, kmc.RECORD_DTYPE), rec], axis=1)
+        results.append(dict(label=label, tile=B, NI=NI, ND=nd, rec=rec, sec=sec,
+                            ticks=n_traj * n_sweeps * per_sweep))
+        if verbose:
+            print(f"[ring] {label}: {n_sweeps} sweeps, {sec:.2f} s", flush=True)
+    return results
+
+
+def analyse_ring(results, N, eq_fraction=0.5, max_lag_samples=200, n_boot=30, boot_seed=0):
+    """tau of A = H m from the equilibrium halves (in steps), eta = tau_REF /
+    tau_PAR and the paper's chi^2 of <A> against the reference (Eq. (efficiency),
+    Eq. (error metric)), with bootstrap errors over trajectories."""
+    rng = np.random.default_rng(boot_seed)
+
+    def A(r):
+        return analysis.observable(r["rec"], N, kind="Hm", n_sites=N)
+
+    def tau_of(r, rows=None):
+        s = r["rec"]["steps"][0].astype(float)
+        a = A(r) if rows is None else A(r)[rows]
+        k0 = int(len(s) * eq_fraction)
+        # runs of 800 steps are only ~14 tau_REF long at equilibrium: centre
+        # on the ensemble mean, which the trajectory means would bias
+        C = analysis.autocorrelation(a[:, k0:], min(max_lag_samples, len(s) - k0 - 1),
+                                     center="ensemble")
+        return analysis.fit_tau(C, s[2] - s[1])
+
+    taus, ses = [], []
+    for r in results:
+        taus.append(tau_of(r))
+        n = r["rec"].shape[0]
+        boot = [tau_of(r, rng.integers(0, n, n)) for _ in range(n_boot)]
+        ses.append(float(np.std(boot)))
+    ref = results[0]
+    s_ref = ref["rec"]["steps"][0].astype(float)
+    A_ref = A(ref)
+    out = []
+    for r, tau, se in zip(results, taus, ses):
+        s = r["rec"]["steps"][0].astype(float)
+        a = A(r)
+        chi2 = analysis.response_error(s_ref, A_ref, s, a, taus[0], tau)
+        chi2_raw = analysis.response_error(s_ref, A_ref, s, a, taus[0], taus[0])
+        eta = analysis.efficiency(taus[0], tau)
+        eta_se = eta * float(np.hypot(ses[0] / taus[0], se / tau)) if r is not ref else 0.0
+        H = analysis.observable(r["rec"], N, kind="H", n_sites=N)
+        k0 = int(H.shape[1] * eq_fraction)
+        out.append(dict(setting=r["label"], N_D=r["ND"], N_I=r["NI"], tau_steps=tau,
+                        tau_se=se, eta=eta, eta_se=eta_se, chi2=chi2, chi2_unscaled=chi2_raw,
+                        e_eq=float(H[:, k0:].mean()), gpu_seconds=r["sec"]))
+    return out
+
+
 def save_study(path, results, L):
     """Trajectories of every setting as compact arrays: M and B fit in 32
     bits for L <= 2^14; steps are shared by all trajectories of a setting."""
@@ -163,6 +267,8 @@ def main():
     from . import kmc
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, default=12)
+    ap.add_argument("--ring", action="store_true",
+                    help="the 1 x 8 ring study (Sec. 3.1) instead of the 2D one")
     ap.add_argument("--traj", type=int, default=0, help="default: Table 1's count")
     ap.add_argument("--steps", type=int, default=0, help="default: Table 1's length")
     ap.add_argument("--seed", type=int, default=2024)
@@ -173,6 +279,16 @@ def main():
     args = ap.parse_args()
     torch.cuda.set_stream(torch.cuda.Stream())
     kmc.use_torch_allocator()
+    if args.ring:
+        N, traj, steps = RING_RUN
+        res = run_ring_study(kmc, N, args.traj or traj, args.steps or steps)
+        for row in analyse_ring(res, N):
+            print(json.dumps(row), flush=True)
+        print(json.dumps({"ring": N, "trajectories": args.traj or traj,
+                          "steps": args.steps or steps,
+                          "gpu_seconds": sum(r["sec"] for r in res),
+                          "site_updates": int(sum(r["ticks"] for r in res))}), flush=True)
+        return
     traj, steps = PAPER_RUNS.get(args.L, (100, 100 * args.L * args.L))
     args.traj = args.traj or traj
     args.steps = args.steps or steps

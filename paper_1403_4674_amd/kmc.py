@@ -39,7 +39,7 @@ class ReplicaDesc(C.Structure):
     _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
                 ("L", C.c_int32), ("tile", C.c_int32), ("steps_per_visit", C.c_int32),
                 ("rate_model", C.c_int32), ("schedule", C.c_int32), ("init", C.c_int32),
-                ("tile_rows", C.c_int32)]
+                ("tile_rows", C.c_int32), ("dims", C.c_int32)]
 
 
 RECORD_DTYPE = np.dtype([("sweep", "<i8"), ("M", "<i8"), ("B", "<i8"),
@@ -147,7 +147,8 @@ def make_descs(descs):
                              int(d.get("rate_model", RATE_METROPOLIS)),
                              int(d.get("schedule", SCHED_RANDOM_PERM)),
                              int(d.get("init", INIT_RANDOM)),
-                             int(d.get("tile_rows", 0)))
+                             int(d.get("tile_rows", 0)),
+                             int(d.get("dims", 0)))
     return arr
 
 
@@ -160,7 +161,7 @@ def kmc_exact_sweeps(desc, p, work, n_sweeps, quantised=True, stream=None):
     in p (a float64 CUDA tensor of 2^(L*L) entries); work: a float64 CUDA
     tensor of 3 * 2^(L*L) entries.  Runs on torch's current stream."""
     import torch
-    n = 1 << (int(desc["L"]) ** 2)
+    n = 1 << (int(desc["L"]) if desc.get("dims", 0) == 1 else int(desc["L"]) ** 2)
     for t, size in ((p, n), (work, 3 * n)):
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() >= size):
             raise ValueError("p and work must be contiguous float64 CUDA tensors of 2^N and 3 2^N")
@@ -177,7 +178,7 @@ def kmc_exact_sweeps_static(desc, p, n_sweeps, quantised=True, stream=None):
     most 16 sites): p is a float64 CUDA tensor of 2^(L*L) entries, updated in
     place on torch's current stream."""
     import torch
-    n = 1 << (int(desc["L"]) ** 2)
+    n = 1 << (int(desc["L"]) if desc.get("dims", 0) == 1 else int(desc["L"]) ** 2)
     if not (p.is_cuda and p.dtype == torch.float64 and p.is_contiguous() and p.numel() >= n):
         raise ValueError("p must be a contiguous float64 CUDA tensor of 2^N entries")
     if stream is None:
@@ -191,7 +192,7 @@ def kmc_exact_sweeps_static(desc, p, n_sweeps, quantised=True, stream=None):
 def kmc_init_lattice(descs, seed, given_spins=None, stream=None):
     """descs: list of dicts with keys L, tile, T and optional J, h,
     steps_per_visit, rate_model, schedule, init, tile_rows (domain height;
-    0 or absent: square domains).  stream: a hipStream_t
+    0 or absent: square domains), dims (1: a ring of L sites).  stream: a hipStream_t
     handle (int) or None for torch's current stream.  Returns the context."""
     arr = make_descs(descs)
     if stream is None:
@@ -244,8 +245,8 @@ def kmc_backward_score(ctx, n_rep, n_bins, out_tensor=None):
     return out
 
 
-def kmc_get_spins(ctx, replica, L):
-    out = np.zeros((L, L), np.int8)
+def kmc_get_spins(ctx, replica, L, ring=False):
+    out = np.zeros((L,) if ring else (L, L), np.int8)
     _check(lib().kmc_get_spins(ctx, replica, _ptr(out)), ctx)
     return out
 
@@ -298,7 +299,8 @@ class Lattice:
         return kmc_observables(self.ctx, self.n_rep)
 
     def spins(self, replica=0):
-        return kmc_get_spins(self.ctx, replica, self.descs[replica]["L"])
+        d = self.descs[replica]
+        return kmc_get_spins(self.ctx, replica, d["L"], d.get("dims", 0) == 1)
 
     def domain_state(self, replica=0):
         return kmc_get_domain_state(self.ctx, replica)

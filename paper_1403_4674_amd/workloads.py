@@ -48,36 +48,55 @@ TUNED_TILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_ti
 
 
 def _tuned(name):
-    """Tile per lattice side chosen for workload `name` by the autotuner
-    (a JSON table next to this file), or None."""
+    """(Bx, By, N_I) per lattice side chosen for workload `name` by the
+    autotuner (a JSON table next to this file), or None.  Entries written
+    before the tuner searched rectangles and visit lengths hold a square side
+    only (N_I = B^2)."""
     if not os.path.exists(TUNED_TILES):
         return None
     with open(TUNED_TILES) as f:
         entry = json.load(f).get(name)
-    return {int(k): int(v) for k, v in entry["tiles"].items()} if entry else None
+    if not entry:
+        return None
+    if "shapes" in entry:
+        return {int(k): tuple(int(x) for x in v) for k, v in entry["shapes"].items()}
+    return {int(k): (int(v), int(v), int(v) ** 2) for k, v in entry["tiles"].items()}
 
 
-def batched_4096(n=4096, tiles=None, seed=4):
+def _desc(L, shape, **kw):
+    bx, by, ni = shape
+    return dict(L=int(L), tile=int(bx), tile_rows=int(by) if by != bx else 0,
+                steps_per_visit=int(ni), rate_model=METROPOLIS, **kw)
+
+
+def batched_4096(n=4096, tiles=None, seed=4, shapes=None):
     """n replicas, L uniform in {16,24,32,48,64,128}, T ~ U[1.5, 3.5],
-    h ~ U[-0.5, 0.5] from numpy default_rng(4); N_I = tile^2; 5000 sweeps."""
+    h ~ U[-0.5, 0.5] from numpy default_rng(4); domain shape and N_I per L
+    from `shapes` {L: (Bx, By, N_I)}, else square `tiles` {L: B} with
+    N_I = B^2, else the autotuner's table, else DEFAULT_TILE; 5000 sweeps."""
     rng = np.random.default_rng(seed)
     Ls = rng.choice([16, 24, 32, 48, 64, 128], size=n)
     Ts = rng.uniform(1.5, 3.5, size=n)
     hs = rng.uniform(-0.5, 0.5, size=n)
-    tiles = tiles or _tuned("batched_4096") or DEFAULT_TILE
-    descs = [dict(L=int(L), tile=int(tiles[int(L)]), J=1.0, h=float(h), T=float(T),
-                  steps_per_visit=0, rate_model=METROPOLIS)
+    if shapes is None and tiles is not None:
+        shapes = {L: (B, B, B * B) for L, B in tiles.items()}
+    shapes = shapes or _tuned("batched_4096") or {L: (B, B, B * B)
+                                                  for L, B in DEFAULT_TILE.items()}
+    descs = [_desc(L, shapes[int(L)], J=1.0, h=float(h), T=float(T))
              for L, T, h in zip(Ls, Ts, hs)]
     return 4, descs, dict(sweeps=5000, record_every=100)
 
 
-def differentiable_1024(n=1024, tile=None, seed=5):
+def differentiable_1024(n=1024, tile=None, seed=5, shape=None):
     """n replicas of 64x64, T=2.5, J=1, h ~ U[-0.2, 0.2] from default_rng(5),
-    N_I = tile^2 (tile tuned, else 32), 20000 sweeps, score on."""
-    if tile is None:
-        tile = (_tuned("differentiable_1024") or {64: 32})[64]
+    domain shape and N_I from `shape` (Bx, By, N_I), else a square `tile`
+    with N_I = tile^2, else the autotuner's table, else 32 x 32 with
+    N_I = 1024; 20000 sweeps, score on."""
+    if shape is None and tile is not None:
+        shape = (tile, tile, tile * tile)
+    if shape is None:
+        shape = (_tuned("differentiable_1024") or {64: (32, 32, 1024)})[64]
     rng = np.random.default_rng(seed)
     hs = rng.uniform(-0.2, 0.2, size=n)
-    descs = [dict(L=64, tile=int(tile), J=1.0, h=float(h), T=2.5, steps_per_visit=0,
-                  rate_model=METROPOLIS) for h in hs]
+    descs = [_desc(64, shape, J=1.0, h=float(h), T=2.5) for h in hs]
     return 5, descs, dict(sweeps=20_000, record_every=10)

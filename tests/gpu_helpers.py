@@ -19,7 +19,7 @@ def oracle_for(kmco, desc, seed, rho, spins=None):
                         rate_model=desc.get("rate_model", 0),
                         schedule=desc.get("schedule", 0), init=desc.get("init", 0),
                         seed=seed, replica=rho, spins=spins,
-                        tile_rows=desc.get("tile_rows", 0))
+                        tile_rows=desc.get("tile_rows", 0), dims=desc.get("dims", 2) or 2)
 
 
 def assert_records_equal(gpu, ora, what=""):
@@ -45,7 +45,7 @@ def assert_replica_equal(lat, rho, ora, gpu_rec=None, ora_rec=None, what=""):
     np.testing.assert_allclose(s + c, os_ + oc, rtol=RTOL_T, atol=0, err_msg=what)
     if gpu_rec is not None:
         assert_records_equal(gpu_rec, ora_rec, what)
-    assert g.shape == (L, L)
+    assert g.shape == ((L,) if lat.descs[rho].get("dims", 0) == 1 else (L, L))
 
 
 def oracle_score(kmco, desc, seed, rho, sweeps, every, pre=0, spins=None):
