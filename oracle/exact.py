@@ -256,3 +256,70 @@ class RingSweepOperator(SweepOperator):
         self.kern = [RingTickKernel(N, d, J, h, T, model, quantise) for d in self.doms]
         self.NI = NI if NI else B
         self.palindrome = palindrome
+
+
+# ------------------------------------------------ time-slice domain processes
+#
+# The rejection-free variant with fixed time slices: a domain process runs
+# its continuous-time kinetics (each site of the domain flips at rate w,
+# nothing outside moves) for a time tau, so it acts on p as exp(Q_d tau),
+# Q_d the domain's generator.  The sweep applies these in colour order.
+
+class SliceKernel:
+    """exp(Q_d tau) of one domain, applied to probability vectors with a
+    sparse matrix exponential (scipy's expm_multiply)."""
+
+    def __init__(self, n_sites, sites, neighbours, J, h, T, model, tau, quantise=True):
+        import scipy.sparse as sp
+        S = ((np.arange(1 << n_sites)[:, None] >> np.arange(n_sites)[None, :]) & 1) * 2 - 1
+        S = S.astype(np.float64)
+        idx = np.arange(1 << n_sites)
+        rows, cols, vals = [], [], []
+        diag = np.zeros(1 << n_sites)
+        for i in sites:
+            n = S[:, neighbours[i]].sum(axis=1)
+            dE = 2.0 * S[:, i] * (J * n + h)
+            w = rate(dE, T, model)
+            if quantise:
+                w = np.minimum(np.floor(w * 2.0 ** 32 + 0.5), 2.0 ** 32) / 2.0 ** 32
+            rows.append(idx ^ (1 << i))
+            cols.append(idx)
+            vals.append(w)
+            diag -= w
+        rows.append(idx)
+        cols.append(idx)
+        vals.append(diag)
+        self.Q = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                               shape=(1 << n_sites, 1 << n_sites))
+        self.tau = tau
+
+    def apply(self, p, times=1):
+        from scipy.sparse.linalg import expm_multiply
+        for _ in range(times):
+            p = expm_multiply(self.Q * self.tau, p)
+        return p
+
+
+class SliceSweepOperator(SweepOperator):
+    """T_PAR of the time-slice variant on the L x L torus (domains Bx x By) or
+    on the ring of L sites (ring=True, domains of Bx sites): each domain
+    visit is exp(Q_d tau); colour orders as for the tick chain."""
+
+    def __init__(self, L, B, J, h, T, model, tau, palindrome=False, By=None, ring=False,
+                 quantise=True):
+        if ring:
+            n_sites = L
+            self.doms, self.cols, self.ncol = ring_partition(L, B)
+            nb = {i: [(i - 1) % L, (i + 1) % L] for i in range(L)}
+        else:
+            n_sites = L * L
+            self.doms, self.cols, self.ncol = partition(L, B, By)
+            nb = {}
+            for i in range(n_sites):
+                y, x = divmod(i, L)
+                nb[i] = [((y - 1) % L) * L + x, ((y + 1) % L) * L + x,
+                         y * L + (x - 1) % L, y * L + (x + 1) % L]
+        self.kern = [SliceKernel(n_sites, d, nb, J, h, T, model, tau, quantise)
+                     for d in self.doms]
+        self.NI = 1
+        self.palindrome = palindrome

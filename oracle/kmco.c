@@ -50,6 +50,28 @@
  *      Word 1 gives the slot (Lemire multiply with rejection, retried on
  *      streams 3..14), word 0 the low 32 bits of x, words 3:2 the 53-bit
  *      uniform for the clock.
+ *  R7  The rejection-free variant with fixed time slices (the synchronous
+ *      time-horizon approaches the paper contrasts itself with, Sec. 1): a
+ *      domain process runs the continuous-time kinetics of its domain, halo
+ *      frozen, for a fixed time tau instead of N_I ticks.  Event k of a visit
+ *      draws one Philox call, counter (k, domain | visit<<20 | 16<<24, sweep,
+ *      replica): words 3:2 give u = (m53 + 1) 2^-53 and the waiting time
+ *      dt = (-ln(u) 2^32) / R (R = sum of the Q32 rates); if t + dt > tau the
+ *      visit ends (the process is still in its state at tau: memoryless);
+ *      otherwise t += dt and words 1:0 give x uniform on [0, R) (Lemire's
+ *      64-bit multiply with rejection, redrawn on streams 17..28), which
+ *      picks the class and member exactly as in R1 -- every draw is an
+ *      event, none is null.  The domain clock advances by tau per visit and
+ *      the step count stays 0.  The stop decision compares FP64 times, so
+ *      the logarithm is one written here from the atanh series
+ *      ln m = 2 atanh((m-1)/(m+1)) after splitting off the binary exponent
+ *      (the GPU library evaluates the same series in the same order):
+ *      both sides then take identical decisions.  With R = 0 (no possible
+ *      event) the visit ends at once.  Each domain process is the
+ *      continuous-time chain observed at a fixed time, whose transition
+ *      matrix exp(Q tau) is reversible with respect to the conditional
+ *      Boltzmann distribution, so Eq. (replica detailed balance) holds for
+ *      it and the reversible schedule keeps the equilibrium exact.
  */
 #include "kmco.h"
 
@@ -62,6 +84,8 @@
 #define STREAM_SCHED 2u
 #define STREAM_RETRY0 3u
 #define MAX_RETRY 12
+#define STREAM_SLICE 16u
+#define STREAM_SLICE_RETRY0 17u
 
 /* ---------------------------------------------------------------- Philox */
 
@@ -222,11 +246,73 @@ uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,
     }
 }
 
+/* ---------------------------------------------------- time-slice variant */
+
+double kmco_slice_log(double u)
+{
+    /* u = m 2^e with m in [sqrt(1/2), sqrt(2)); f = m - 1 is exact
+     * (Sterbenz); s = f / (2 + f); ln m = 2 s (1 + z/3 + z^2/5 + ...),
+     * z = s^2 <= 0.0295, twelve terms; ln u = e ln2_hi + (ln m + e ln2_lo)
+     * with ln2_hi holding 32 significant bits, so e ln2_hi is exact. */
+    const double ln2_hi = 0x1.62e42ffp-1;
+    const double ln2_lo = -0x1.718432a1b0e26p-35;
+    uint64_t bits;
+    memcpy(&bits, &u, sizeof bits);
+    int e = (int)((bits >> 52) & 0x7FF) - 1023;
+    bits = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull; /* m in [1, 2) */
+    double m;
+    memcpy(&m, &bits, sizeof m);
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double f = m - 1.0;
+    double sv = f / (2.0 + f);
+    double z = sv * sv;
+    double q = 1.0 / 25.0;
+    q = 1.0 / 23.0 + z * q;
+    q = 1.0 / 21.0 + z * q;
+    q = 1.0 / 19.0 + z * q;
+    q = 1.0 / 17.0 + z * q;
+    q = 1.0 / 15.0 + z * q;
+    q = 1.0 / 13.0 + z * q;
+    q = 1.0 / 11.0 + z * q;
+    q = 1.0 / 9.0 + z * q;
+    q = 1.0 / 7.0 + z * q;
+    q = 1.0 / 5.0 + z * q;
+    q = 1.0 / 3.0 + z * q;
+    double two_s = sv + sv;
+    double lm = two_s + (two_s * z) * q;
+    double de = (double)e;
+    return de * ln2_hi + (lm + de * ln2_lo);
+}
+
+/* x uniform on [0, R), R > 0, from the 64-bit word w1:w0 of event k:
+ * Lemire's multiply-high with rejection of the (2^64 mod R) smallest low
+ * products, redrawn from the retry streams (words 1:0 of each call). */
+static uint64_t slice_select(uint64_t seed, int32_t replica, int64_t sweep,
+                             uint32_t c1, uint32_t k, uint64_t R,
+                             uint32_t w1, uint32_t w0)
+{
+    uint64_t word = ((uint64_t)w1 << 32) | w0;
+    for (int r = 0;; ++r) {
+        unsigned __int128 m = (unsigned __int128)word * R;
+        uint64_t lo = (uint64_t)m;
+        if (lo >= R || lo >= (0 - R) % R || r == MAX_RETRY)
+            return (uint64_t)(m >> 64);
+        uint32_t o[4];
+        draw(seed, k, c1 | ((STREAM_SLICE_RETRY0 + (uint32_t)r) << 24), (uint32_t)sweep,
+             (uint32_t)replica, o);
+        word = ((uint64_t)o[1] << 32) | o[0];
+    }
+}
+
 /* ---------------------------------------------------------------- state */
 
 struct kmco_state {
     int L, Bx, By, NTx, NTy, ND, nd, NI, sched, model;
     int Ly;                /* lattice rows: L, or 1 for the ring          */
+    double tau;            /* time slice per visit; 0: N_I ticks (R7)     */
     int z;                 /* neighbours per site: 4, or 2 on the ring    */
     int ncol;              /* colours of the domain grid                  */
     int32_t *colour;       /* [ND]                                        */
@@ -291,6 +377,12 @@ kmco_state *kmco_create(const kmco_desc *d, uint64_t seed, int32_t replica,
     s->ND = s->NTx * s->NTy;
     s->nd = s->Bx * s->By;
     s->NI = d->steps_per_visit ? d->steps_per_visit : s->nd;
+    if (!(d->time_slice >= 0.0) || !isfinite(d->time_slice)) {
+        free(s);
+        return NULL;
+    }
+    s->tau = d->time_slice;
+    if (s->tau > 0.0) s->NI = 0; /* no ticks: the step count stays 0 */
     s->sched = d->schedule; s->model = d->rate_model;
     s->J = d->J; s->h = d->h; s->T = d->T;
     s->seed = seed; s->replica = replica;
@@ -447,13 +539,54 @@ static void check_classes(kmco_state *s, int oy, int ox, const int64_t n[10])
         if (cnt[c] != n[c]) s->check_fail++;
 }
 
+/* The site an event at x < R picks (R1): the rate class c is the first
+ * whose prefix sum exceeds x, the member the j-th of that class in ascending
+ * local index, j = floor((x - P_{c-1}) / r_c).  Returns the local index. */
+static int pick_site(const kmco_state *s, const int64_t n[10], uint64_t x, int *cls)
+{
+    int c = 0;
+    uint64_t P = 0;
+    while (x >= P + (uint64_t)n[c] * s->r[c]) {
+        P += (uint64_t)n[c] * s->r[c];
+        ++c;
+    }
+    uint64_t j = (x - P) / s->r[c];
+    *cls = c;
+    return select_member(s, c, j);
+}
+
+/* Flips local site k of domain d (origin oy, ox) and moves it and its
+ * neighbours inside the domain to their new classes; halo sites stay. */
+static void flip_site(kmco_state *s, int d, int oy, int ox, int k, int64_t n[10], int flags)
+{
+    const int Bx = s->Bx, By = s->By, L = s->L;
+    int gy = oy + k / Bx, gx = ox + k % Bx;
+    int aff[5], na = 0;
+    const int dy[5] = {0, 0, 0, -1, 1}, dx[5] = {0, -1, 1, 0, 0};
+    for (int a = 0; a < 1 + s->z; ++a) {
+        int yy = wrap(gy + dy[a], s->Ly), xx = wrap(gx + dx[a], L);
+        int ry = wrap(yy - oy, s->Ly), rx = wrap(xx - ox, L);
+        if (ry >= By || rx >= Bx) continue; /* halo site: frozen */
+        int kk = ry * Bx + rx, dup = 0;
+        for (int b = 0; b < na; ++b) dup |= aff[b] == kk;
+        if (!dup) aff[na++] = kk;
+    }
+    for (int a = 0; a < na; ++a) clear_class(s, aff[a], n);
+    s->spin[gy * L + gx] = (int8_t)-s->spin[gy * L + gx];
+    for (int a = 0; a < na; ++a)
+        set_class(s, aff[a], site_class(s, oy + aff[a] / Bx, ox + aff[a] % Bx), n);
+    s->events++;
+    s->dom_events[d]++;
+    if (flags & KMCO_F_CHECK) check_classes(s, oy, ox, n);
+}
+
 /* Runs one domain process: N_I ticks of domain d with everything outside the
  * domain held fixed (the halo is read from the lattice, which no other
  * domain changes during the visit). */
 static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
                          int flags, double *score, double *score_abs)
 {
-    const int Bx = s->Bx, By = s->By, L = s->L;
+    const int Bx = s->Bx, By = s->By;
     const int oy = (d / s->NTx) * By, ox = (d % s->NTx) * Bx;
     int64_t n[10] = {0};
     memset(s->bits, 0, sizeof(uint64_t) * 10 * (size_t)s->nw);
@@ -482,16 +615,8 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
             continue;
         }
         /* event: rate class by prefix, then member j of that class */
-        int c = 0;
-        uint64_t P = 0;
-        while (x >= P + (uint64_t)n[c] * s->r[c]) {
-            P += (uint64_t)n[c] * s->r[c];
-            ++c;
-        }
-        uint64_t j = (x - P) / s->r[c];
-        int k = select_member(s, c, j);
-        int ly = k / Bx, lx = k % Bx;
-        int gy = oy + ly, gx = ox + lx;
+        int c;
+        int k = pick_site(s, n, x, &c);
 
         if (flags & KMCO_F_SCORE) {
             if (m_null) {
@@ -522,24 +647,7 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         neumaier_add(&s->clk_sum[d], &s->clk_comp[d], dt);
 
         /* the flipped site and its neighbours inside the domain change class */
-        int aff[5], na = 0;
-        const int dy[5] = {0, 0, 0, -1, 1}, dx[5] = {0, -1, 1, 0, 0};
-        for (int a = 0; a < 1 + s->z; ++a) {
-            int yy = wrap(gy + dy[a], s->Ly), xx = wrap(gx + dx[a], L);
-            int ry = wrap(yy - oy, s->Ly), rx = wrap(xx - ox, L);
-            if (ry >= By || rx >= Bx) continue; /* halo site: frozen */
-            int kk = ry * Bx + rx, dup = 0;
-            for (int b = 0; b < na; ++b) dup |= aff[b] == kk;
-            if (!dup) aff[na++] = kk;
-        }
-        for (int a = 0; a < na; ++a) clear_class(s, aff[a], n);
-        s->spin[gy * L + gx] = (int8_t)-s->spin[gy * L + gx];
-        for (int a = 0; a < na; ++a)
-            set_class(s, aff[a],
-                      site_class(s, oy + aff[a] / Bx, ox + aff[a] % Bx), n);
-        s->events++;
-        s->dom_events[d]++;
-        if (flags & KMCO_F_CHECK) check_classes(s, oy, ox, n);
+        flip_site(s, d, oy, ox, k, n, flags);
     }
     if ((flags & KMCO_F_SCORE) && m_null) {
         double nu[2];
@@ -554,6 +662,38 @@ static void visit_domain(kmco_state *s, int d, int visit, int64_t w,
         }
     }
     s->steps += s->NI;
+}
+
+/* The time-slice form of a domain process (R7): rejection-free events of
+ * domain d until its clock would pass tau. */
+static void visit_slice(kmco_state *s, int d, int visit, int64_t w, int flags)
+{
+    const int Bx = s->Bx, By = s->By;
+    const int oy = (d / s->NTx) * By, ox = (d % s->NTx) * Bx;
+    const uint32_t c1 = (uint32_t)d | ((uint32_t)visit << 20);
+    int64_t n[10] = {0};
+    memset(s->bits, 0, sizeof(uint64_t) * 10 * (size_t)s->nw);
+    for (int k = 0; k < s->nd; ++k)
+        set_class(s, k, site_class(s, oy + k / Bx, ox + k % Bx), n);
+    double t = 0.0;
+    for (uint32_t ev = 0;; ++ev) {
+        uint64_t R = 0;
+        for (int c = 0; c < 10; ++c) R += (uint64_t)n[c] * s->r[c];
+        if (R == 0) break; /* no event can happen: the state holds to tau */
+        uint32_t o[4];
+        draw(s->seed, ev, c1 | (STREAM_SLICE << 24), (uint32_t)w, (uint32_t)s->replica, o);
+        uint64_t u53 = ((uint64_t)o[3] << 21) | (o[2] >> 11);
+        double u = (double)(u53 + 1) * 0x1p-53;
+        double dt = (-kmco_slice_log(u) * 4294967296.0) / (double)R;
+        double tn = t + dt;
+        if (tn > s->tau) break; /* the next event falls after the slice */
+        t = tn;
+        uint64_t x = slice_select(s->seed, s->replica, w, c1, ev, R, o[1], o[0]);
+        int c;
+        int k = pick_site(s, n, x, &c);
+        flip_site(s, d, oy, ox, k, n, flags);
+    }
+    neumaier_add(&s->clk_sum[d], &s->clk_comp[d], s->tau);
 }
 
 static void observe(const kmco_state *s, kmco_record *r)
@@ -582,6 +722,7 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
 {
     if (!s || n_sweeps < 0 || record_every < 1) return -1;
     if ((flags & KMCO_F_SCORE) && !score) return -1;
+    if ((flags & KMCO_F_SCORE) && s->tau > 0.0) return -1; /* no score for R7 */
     const int nc = s->ncol;
     int64_t nrec = 0;
     double dummy[2], dummy_abs[2];
@@ -615,8 +756,12 @@ int64_t kmco_run(kmco_state *s, int64_t n_sweeps, int32_t record_every,
                          : NULL;
         for (int p = 0; p < nphase; ++p) {
             for (int d = 0; d < s->ND; ++d)
-                if (s->colour[d] == order[p])
-                    visit_domain(s, d, visit[p], w, flags, sc, sa);
+                if (s->colour[d] == order[p]) {
+                    if (s->tau > 0.0)
+                        visit_slice(s, d, visit[p], w, flags);
+                    else
+                        visit_domain(s, d, visit[p], w, flags, sc, sa);
+                }
         }
         s->sweep++;
         if ((i + 1) % record_every == 0) {

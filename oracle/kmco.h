@@ -52,6 +52,11 @@ typedef struct {
     int32_t dims;            /* 0 or 2: periodic L x L lattice; 1: periodic
                                 ring of L sites (Sec. 3.1), domains of
                                 `tile` sites, tile_rows 0 or 1              */
+    double time_slice;       /* > 0: the rejection-free variant with fixed
+                                time slices (see kmco.c, R7): each domain
+                                process runs its continuous-time kinetics
+                                for this long instead of N_I ticks; 0: the
+                                tick chain                                 */
 } kmco_desc;
 
 typedef struct {
@@ -90,6 +95,12 @@ void kmco_perm_from_index(int32_t idx, int32_t perm[4]);
  * (t mod 2), 3 for an odd count (t mod 2, the last domain 2); the domain's
  * colour is ax + cx * ay. */
 int kmco_get_partition(const kmco_state *s, int32_t *colour, int32_t *n_colours);
+
+/* Natural logarithm of u in (0, 1] by the atanh series (R7): the same
+ * sequence of IEEE double operations as the GPU library's, so both take
+ * identical time-slice decisions.  Within 2 ulp of the correctly rounded
+ * value (tested against libm). */
+double kmco_slice_log(double u);
 
 /* Uniform slot in [0, n) for one tick, with rejection and retries. */
 uint32_t kmco_tick_slot(uint64_t seed, int32_t replica, int64_t sweep,

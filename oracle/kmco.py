@@ -20,7 +20,7 @@ class Desc(C.Structure):
                 ("L", C.c_int32), ("tile", C.c_int32),
                 ("steps_per_visit", C.c_int32), ("rate_model", C.c_int32),
                 ("schedule", C.c_int32), ("init", C.c_int32),
-                ("tile_rows", C.c_int32), ("dims", C.c_int32)]
+                ("tile_rows", C.c_int32), ("dims", C.c_int32), ("time_slice", C.c_double)]
 
 
 class Record(C.Structure):
@@ -67,6 +67,8 @@ def lib():
         L.kmco_check_failures.argtypes = [P]
         L.kmco_check_failures.restype = C.c_int64
         L.kmco_get_retries.argtypes = [P, P, P]
+        L.kmco_slice_log.argtypes = [C.c_double]
+        L.kmco_slice_log.restype = C.c_double
         L.kmco_count_retry_ticks.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32,
                                              C.c_int32, C.c_uint32, C.c_uint32]
         L.kmco_count_retry_ticks.restype = C.c_int64
@@ -116,6 +118,11 @@ def perm_from_index_n(idx, n):
     return p
 
 
+def slice_log(u):
+    """The logarithm the time-slice variant decides with (kmco_slice_log)."""
+    return lib().kmco_slice_log(float(u))
+
+
 def count_retry_ticks(seed, replica, sweep, domain, visit, n_ticks, n):
     """Ticks t < n_ticks of one visit whose slot in [0, n) is redrawn."""
     return lib().kmco_count_retry_ticks(seed, replica, sweep, domain, visit, n_ticks, n)
@@ -133,9 +140,10 @@ class Replica:
 
     def __init__(self, L, tile, J=1.0, h=0.0, T=2.5, steps_per_visit=0,
                  rate_model=METROPOLIS, schedule=SCHED_RANDOM_PERM,
-                 init=INIT_RANDOM, seed=1, replica=0, spins=None, tile_rows=0, dims=2):
+                 init=INIT_RANDOM, seed=1, replica=0, spins=None, tile_rows=0, dims=2,
+                 time_slice=0.0):
         self.desc = Desc(J, h, T, L, tile, steps_per_visit, rate_model,
-                         schedule, init, tile_rows, dims)
+                         schedule, init, tile_rows, dims, time_slice)
         self.L, self.tile = L, tile
         self.ring = dims == 1
         self.tile_rows = 1 if self.ring else (tile_rows or tile)
