@@ -135,6 +135,25 @@ typedef struct {
                                   dE = 2 s (J (2k - 2) + h).  Rings run in
                                   the phase, dataflow and persistent forms
                                   (the resident form: KMC_EUNSUPPORTED)     */
+    double time_slice;         /* > 0: the rejection-free variant with fixed
+                                  time slices (the synchronous time-horizon
+                                  methods the paper contrasts its own with,
+                                  Sec. 1): each domain process runs its
+                                  continuous-time kinetics (site flip rates
+                                  w, residence times -ln(u)/R, every event
+                                  real) for this long instead of N_I ticks;
+                                  the domain clocks advance by time_slice
+                                  per visit and `steps` stays 0.  Event k
+                                  of a visit draws Philox counter (k, domain
+                                  | visit<<20 | 16<<24, sweep, replica):
+                                  words 3:2 the waiting time, words 1:0 the
+                                  event by Lemire's 64-bit multiply with
+                                  rejection (redraws on streams 17..28).
+                                  All replicas of a context use it or none
+                                  (KMC_EINVAL); phase, dataflow and
+                                  one-domain-per-wavefront persistent forms
+                                  only; no score, checkpoint or resident form
+                                  (KMC_EUNSUPPORTED).  0: the tick chain   */
 } kmc_replica_desc;
 
 /* Observables at a sweep endpoint, the only points where statistics are

@@ -76,6 +76,8 @@ struct kmc_ctx {
     // per row-mask width (B <= 32, B > 32): some replica is one periodic
     // domain, so the launches of that width take the wrap-around kernels
     bool wrap[2] = {false, false};
+    // every replica runs the time-slice variant (time_slice > 0)
+    bool slice = false;
     int n_phase = 1;  // colour phases per sweep, the largest over the replicas
 
     Rep *d_reps = nullptr;
@@ -260,7 +262,7 @@ int max_per_colour(const Rep &rp) { return axis_most(rp.NT) * axis_most(rp.NTy);
 // Replicas the multi-slot kernel runs: square domains of at most 16 x 16 on a
 // 4-colour checkerboard.
 bool multi_ok(const Rep &rp) {
-    return rp.z == 4 && rp.B <= 16 && rp.By == rp.B && rp.NT >= 2 && rp.NT % 2 == 0 &&
+    return rp.z == 4 && rp.tau == 0.0 && rp.B <= 16 && rp.By == rp.B && rp.NT >= 2 && rp.NT % 2 == 0 &&
            rp.NTy == rp.NT;
 }
 
@@ -283,6 +285,8 @@ void validate(kmc_ctx *c, const kmc_replica_desc &d, int rho) {
     if (!std::isfinite(d.J) || !std::isfinite(d.h) || !std::isfinite(d.T) || !(d.T > 0))
         bad("J, h must be finite and T > 0");
     if (d.dims != 0 && d.dims != 1 && d.dims != 2) bad("dims must be 0, 1 or 2");
+    if (!std::isfinite(d.time_slice) || !(d.time_slice >= 0.0))
+        bad("time_slice must be finite and >= 0");
     if (is_ring(d)) {
         if (d.tile_rows != 0 && d.tile_rows != 1) bad("a ring's tile_rows must be 0 or 1");
         if (d.tile < 1 || d.tile > 64) bad("a ring's tile must be in [1, 64]");
@@ -375,6 +379,19 @@ void with_wrap(const kmc_ctx *c, int g, F f) {
         f(std::false_type{});
 }
 
+// Calls f(wrap, slice) with the context's wrap-around and time-slice kinds
+// as std::true_type / std::false_type (the time-slice kernels exist without
+// the score only).
+template <bool SCORE, typename F>
+void with_kind(const kmc_ctx *c, int g, F f) {
+    with_wrap(c, g, [&](auto W) {
+        if (!SCORE && c->slice)
+            f(W, std::true_type{});
+        else
+            f(W, std::false_type{});
+    });
+}
+
 template <bool SCORE>
 void launch_sweep(kmc_ctx *c, KParams K);
 
@@ -405,8 +422,9 @@ void launch_flow(kmc_ctx *c, KParams K, int G) {
     timed_launch(c, [&] {
         if (c->n_tasks32) {
             K.task_begin = 0;
-            with_wrap(c, 0, [&](auto W) {
-                hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value>),
+            with_kind<SCORE>(c, 0, [&](auto W, auto S) {
+                hipLaunchKernelGGL((kmcdev::k_flow<uint32_t, SCORE, decltype(W)::value,
+                                                   decltype(S)::value && !SCORE>),
                                    dim3(flow_blocks(c, G, c->n_tasks32)), dim3(64), 0,
                                    c->stream, K, c->n_tasks32, c->n_phase, c->d_done);
             });
@@ -415,8 +433,9 @@ void launch_flow(kmc_ctx *c, KParams K, int G) {
         if (c->n_tasks > c->n_tasks32) {
             const int nt = c->n_tasks - c->n_tasks32;
             K.task_begin = c->n_tasks32;
-            with_wrap(c, 1, [&](auto W) {
-                hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value>),
+            with_kind<SCORE>(c, 1, [&](auto W, auto S) {
+                hipLaunchKernelGGL((kmcdev::k_flow<uint64_t, SCORE, decltype(W)::value,
+                                                   decltype(S)::value && !SCORE>),
                                    dim3(flow_blocks(c, G, nt)), dim3(64), 0, c->stream, K, nt,
                                    c->n_phase, c->d_done);
             });
@@ -452,15 +471,17 @@ void launch_sweep(kmc_ctx *c, KParams K) {
         timed_launch(c, [&] {
         if (c->n_tasks32) {
             K.task_begin = 0;
-            with_wrap(c, 0, [&](auto W) {
-                hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE, decltype(W)::value>),
+            with_kind<SCORE>(c, 0, [&](auto W, auto S) {
+                hipLaunchKernelGGL((kmcdev::k_phase<uint32_t, SCORE, decltype(W)::value,
+                                                    decltype(S)::value && !SCORE>),
                                    dim3(c->n_tasks32), dim3(64), 0, c->stream, K, p);
             });
         }
         if (c->n_tasks > c->n_tasks32) {
             K.task_begin = c->n_tasks32;
-            with_wrap(c, 1, [&](auto W) {
-                hipLaunchKernelGGL((kmcdev::k_phase<uint64_t, SCORE, decltype(W)::value>),
+            with_kind<SCORE>(c, 1, [&](auto W, auto S) {
+                hipLaunchKernelGGL((kmcdev::k_phase<uint64_t, SCORE, decltype(W)::value,
+                                                    decltype(S)::value && !SCORE>),
                                    dim3(c->n_tasks - c->n_tasks32), dim3(64), 0, c->stream, K,
                                    p);
             });
@@ -494,13 +515,16 @@ void launch_persistent(kmc_ctx *c, KParams K, int64_t n_sweeps, uint32_t flags) 
         const int groups = std::max(1, std::min(nt[g] + (ns[g] + waves - 1) / waves, cus * 8));
         hipLaunchKernelGGL(kmcdev::k_reset_queue, dim3(1), dim3(1), 0, c->stream, K.ctl);
         timed_launch(c, [&] {
-            with_wrap(c, g, [&](auto W) {
+            with_kind<SCORE>(c, g, [&](auto W, auto S) {
+                constexpr bool SL = decltype(S)::value && !SCORE;
                 if (g == 0)
-                    hipLaunchKernelGGL((kmcdev::k_persistent<uint32_t, SCORE, decltype(W)::value>),
-                                       dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
+                    hipLaunchKernelGGL(
+                        (kmcdev::k_persistent<uint32_t, SCORE, decltype(W)::value, SL>),
+                        dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
                 else
-                    hipLaunchKernelGGL((kmcdev::k_persistent<uint64_t, SCORE, decltype(W)::value>),
-                                       dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
+                    hipLaunchKernelGGL(
+                        (kmcdev::k_persistent<uint64_t, SCORE, decltype(W)::value, SL>),
+                        dim3(groups), dim3(64 * waves), 0, c->stream, K, n_sweeps);
             });
         });
     }
@@ -712,6 +736,7 @@ struct ExactPlan {
 // Validates d and fills the plan; KMC_OK, KMC_EINVAL or KMC_EUNSUPPORTED.
 kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, ExactPlan &P) {
     validate(nullptr, *d, 0);  // throws Fail{KMC_EINVAL}
+    if (d->time_slice > 0.0) return KMC_EUNSUPPORTED;  // propagates the tick chain only
     const bool ring = is_ring(*d);
     const int L = d->L, Ly = rows_of(*d), N = L * Ly;
     if (N > max_sites) return KMC_EINVAL;
@@ -910,6 +935,8 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             rp.nperm = 1;
             for (int k = 2; k <= rp.ncol; ++k) rp.nperm *= k;
             rp.NI = q.steps_per_visit ? q.steps_per_visit : q.tile * rp.By;
+            rp.tau = q.time_slice;
+            if (rp.tau > 0.0) rp.NI = 0;  // no ticks: the step count stays 0
             rp.sched = q.schedule;
             rp.ND = rp.NT * rp.NTy;
             rp.nd = (uint32_t)(q.tile * rp.By);
@@ -938,6 +965,11 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
             }
         }
         if (any_given && !given_spins) fail(c, KMC_EINVAL, "KMC_INIT_GIVEN needs given_spins");
+        c->slice = d[0].time_slice > 0.0;
+        for (int rho = 1; rho < n_rep; ++rho)
+            if ((d[rho].time_slice > 0.0) != c->slice)
+                fail(c, KMC_EINVAL,
+                     "all replicas of a context run time slices (time_slice > 0) or none");
         c->spin_bytes = off;
         c->n_dom = dom;
 
@@ -1126,6 +1158,9 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
             fail(c, KMC_EINVAL, "sweep counter would exceed 2^32 - 1");
         if ((flags & KMC_F_SCORE) && (flags & KMC_F_GRAPH))
             fail(c, KMC_EINVAL, "KMC_F_SCORE is not available with KMC_F_GRAPH");
+        if (c->slice && (flags & (KMC_F_SCORE | KMC_F_CHECKPOINT | KMC_F_RESIDENT)))
+            fail(c, KMC_EUNSUPPORTED,
+                 "the time-slice variant runs without score, checkpoint or the resident form");
         if ((flags & KMC_F_TIMING) && (flags & KMC_F_GRAPH))
             fail(c, KMC_EINVAL, "KMC_F_TIMING is not available with KMC_F_GRAPH");
         if ((flags & KMC_F_FLOW) && (flags & KMC_F_PERSISTENT))

@@ -42,6 +42,10 @@ constexpr uint32_t kStreamInit = 1;
 constexpr uint32_t kStreamSched = 2;
 constexpr uint32_t kStreamRetry0 = 3;
 constexpr int kMaxRetry = 12;
+// the time-slice variant: one call per event, redraws of its 64-bit
+// selection word on streams 17 .. 28
+constexpr uint32_t kStreamSlice = 16;
+constexpr uint32_t kStreamSliceRetry0 = 17;
 
 constexpr int kLdsPerWave = 64 * 64 + 2 * 64;  // tile + top/bottom halo rows
 constexpr int kWavesPerPersistentGroup = 4;
@@ -68,6 +72,8 @@ struct Rep {
     int32_t init;           // kmc_init kind
     int32_t z;              // neighbours per site: 4 (L x L lattice) or 2 (ring
                             // of L sites: one row, By = NTy = 1)
+    double tau;             // time slice of a domain process (> 0: the
+                            // rejection-free variant; NI = 0 then)
 };
 
 // Sites of a replica's lattice: L^2, or L on the ring.
@@ -632,6 +638,46 @@ __device__ __forceinline__ void planes_step(Planes<MT> &P, MT m, bool inc) {
     planes_step_inv<MT>(P, m, inc ? (MT)0 : ~(MT)0);
 }
 
+// Natural logarithm of u in (0, 1] for the stop decisions of the time-slice
+// variant, by the atanh series: u = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// f = m - 1 (exact), s = f / (2 + f), ln m = 2 s (1 + z/3 + z^2/5 + ...) with
+// z = s^2 <= 0.0295 (twelve terms), ln u = e ln2_hi + (ln m + e ln2_lo) where
+// ln2_hi holds 32 significant bits (e ln2_hi is exact).  Only IEEE additions,
+// multiplications and correctly rounded divisions, in a fixed order and
+// without contraction, so the value is reproducible bit for bit by any
+// implementation of the same steps; within 2 ulp of ln u.
+__device__ __forceinline__ double slice_log(double u) {
+    const double ln2_hi = 0x1.62e42ffp-1;
+    const double ln2_lo = -0x1.718432a1b0e26p-35;
+    const uint64_t bits = (uint64_t)__double_as_longlong(u);
+    int e = (int)((bits >> 52) & 0x7FF) - 1023;
+    double m = __longlong_as_double(
+        (long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double f = m - 1.0;
+    const double sv = f / (2.0 + f);
+    const double z = sv * sv;
+    double q = 1.0 / 25.0;
+    q = 1.0 / 23.0 + z * q;
+    q = 1.0 / 21.0 + z * q;
+    q = 1.0 / 19.0 + z * q;
+    q = 1.0 / 17.0 + z * q;
+    q = 1.0 / 15.0 + z * q;
+    q = 1.0 / 13.0 + z * q;
+    q = 1.0 / 11.0 + z * q;
+    q = 1.0 / 9.0 + z * q;
+    q = 1.0 / 7.0 + z * q;
+    q = 1.0 / 5.0 + z * q;
+    q = 1.0 / 3.0 + z * q;
+    const double two_s = sv + sv;
+    const double lm = two_s + (two_s * z) * q;
+    const double de = (double)e;
+    return de * ln2_hi + (lm + de * ln2_lo);
+}
+
 // m / den for the score of a run of m null ticks (den > 0): the hardware
 // reciprocal refined by two Newton steps (within an ulp of 1/den), times m.
 // Cheaper than the correctly rounded quotient.  Every form of the score
@@ -662,7 +708,7 @@ struct VisitOut {
 // is a single periodic domain; without it the wrap-around bookkeeping is
 // compiled out of the event chain (every instruction of the chain costs an
 // issue slot when a wavefront runs alone on its SIMD).
-template <typename MT, bool SCORE, bool WRAP>
+template <typename MT, bool SCORE, bool WRAP, bool SLICE = false>
 __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                                  const Rates *__restrict__ rt, int oy, int ox,
                                  uint32_t d, uint32_t vis, uint32_t w,
@@ -783,161 +829,218 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         if (den > 0.0) A_lane += null_quot(m, den) * nl;
     };
 
-    for (int base = 0; base < NI; base += 64) {
-        const uint32_t t = (uint32_t)(base + lane);
-        const bool valid = base + lane < NI;
-        const uint4 o = philox(t, c1, w, rho, key0, key1);
-        uint64_t mm = (uint64_t)o.y * nd;
-        bool rej = valid && (uint32_t)mm < thr;
-        if (__ballot(rej)) {  // rare: redraw the slot on the retry streams
-            for (int k = 1; rej && k <= kMaxRetry; ++k) {
-                const uint4 o2 =
-                    philox(t, d | (vis << 20) | ((kStreamRetry0 + k - 1) << 24), w,
-                           rho, key0, key1);
-                mm = (uint64_t)o2.y * nd;
-                rej = (uint32_t)mm < thr;
-            }
+    // One event at x_e (held as x_e + 1/2): rate class, member, flip and the
+    // class bookkeeping of the flipped site and its in-tile neighbours.
+    auto event = [&](const double xe) {
+        // rate class: first c with x_e < P_c (lane 9 holds R > x_e).
+        // Member index j = floor((x_e - P_{c-1}) / r_c), formed in every
+        // class lane at once as trunc((x_e + 1/2 - P_{c-1}) fl(1/r_c)): the
+        // quotient lies at least 1/(2 r_c) >= 2^-33 from an integer and
+        // the product is within 2^-39 of it (quotient < 2^13), so the
+        // truncation is exact.  Only lane c's quotient is read, then
+        // converted.
+        const int c = __builtin_ctzll(__ballot(xe < Pinc));
+        const double q = (xe - (Pinc - W)) * inv_lane;
+        const uint32_t j = (uint32_t)rdl_f64(q, c);
+
+        if constexpr (SCORE) {
+            if (m_null) null_run(m_null);
         }
-        // x = slot 2^32 + w0, exact in a double, held as xh = x + 1/2: the
-        // comparisons with the integer sums R and P_c are unchanged by the
-        // half, and the member quotient below starts from it
-        const double xh = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x + 0.5;
-        uint64_t left = __ballot(valid);  // ticks of the batch not yet decided
-        double Rb = 0.0;                  // this lane's R before its event (0: none)
-        int pos = 0;
-        // the first undecided tick below R is the next event; the ticks
-        // before it are nulls
-        uint64_t cand = __ballot(xh < R) & left;
-        while (cand) {
-            const int e = __builtin_ctzll(cand);
-            left &= ~1ull << e;  // drop the ticks up to and including e
-            m_null += (uint32_t)(e - pos);
-            const double xe = rdl_f64(xh, e);  // x_e + 1/2
-            if (lane == e) Rb = R;
+        m_null = 0;
 
-            // rate class: first c with x_e < P_c (lane 9 holds R > x_e).
-            // Member index j = floor((x_e - P_{c-1}) / r_c), formed in every
-            // class lane at once as trunc((x_e + 1/2 - P_{c-1}) fl(1/r_c)): the
-            // quotient lies at least 1/(2 r_c) >= 2^-33 from an integer and
-            // the product is within 2^-39 of it (quotient < 2^13), so the
-            // truncation is exact.  Only lane c's quotient is read, then
-            // converted.
-            const int c = __builtin_ctzll(__ballot(xe < Pinc));
-            const double q = (xe - (Pinc - W)) * inv_lane;
-            const uint32_t j = (uint32_t)rdl_f64(q, c);
-
-            if constexpr (SCORE) {
-                if (m_null) null_run(m_null);
-            }
-            m_null = 0;
-
-            // member j of class c in ascending row-major order: the row by a
-            // scan of per-row counts, the column by counting the row's
-            // members below each lane (mbcnt)
-            const MT cm = class_mask<MT>(class_sel(c), S, P, VM);
-            const uint32_t cnt = (uint32_t)popc(cm);
-            const uint32_t incl = sizeof(MT) == 4 ? scan32(cnt) : scan64(cnt);
-            const int ys = __builtin_ctzll(__ballot(incl > j));
-            const uint32_t jr = j - rdl32(incl - cnt, ys);
-            int xs;
-            if constexpr (sizeof(MT) == 8) {
-                const uint64_t row = rdl64(cm, ys);
-                xs = __builtin_ctzll(__ballot(bits_below_lane(row) == jr) & row);
-            } else {
-                const uint32_t row = rdl32(cm, ys);
-                xs = __builtin_ctzll(
-                    __ballot(__builtin_amdgcn_mbcnt_lo(row, 0u) == jr) & (uint64_t)row);
-            }
-
-            // class changes of the flipped site and its in-tile neighbours as
-            // packed 3-bit per-class tallies (10 classes in 30 bits): row ys
-            // holds the sites at columns xs -/+ 1, rows ys -/+ 1 the site at
-            // column xs; the three rows are summed into row ys by DPP
-            // neighbour rows and columns; outside the tile (-1 or B) they are
-            // halo and frozen, unless the lattice is one periodic domain
-            // upm: all ones when the flipped spin is +1 (c >= 5), whose
-            // neighbours then lose an up neighbour; the flipped site moves
-            // to class c -/+ 5 (tally field 3 c -/+ 15)
-            const uint32_t upm = sgpr_sign_bit<0x3E0>((uint32_t)c);
-            const int c3 = 3 * c;
-            const int c3_new = c3 + 15 - (int)(upm & 30u);
-            const bool on_row = lane == ys;
-            constexpr int NB = 8 * (int)sizeof(MT);
-            int ym = ys - 1, yp = ys + 1, xm = xs - 1, xp = xs + 1;
-            bool adj;
-            MT nm = 0;    // this lane's neighbours of the flipped site
-            uint32_t nb;  // their classes as tallies
-            if constexpr (!WRAP) {
-                // row ys: columns xs -/+ 1 inside the tile; rows ys -/+ 1:
-                // column xs.  Each lane reads its sites at xa (xs - 1 on row
-                // ys, else xs) and xb = xs + 1; a column outside the tile, or
-                // not this lane's, is a clear bit of nm
-                const MT bx = (MT)1 << xs;
-                const MT mrow = ((bx << 1) | (bx >> 1)) & vm_row;
-                adj = (lane == ym || lane == yp) && lane < By;
-                nm = on_row ? mrow : (adj ? bx : (MT)0);
-                const int xa = (xs - (on_row ? 1 : 0)) & (NB - 1), xb = (xs + 1) & (NB - 1);
-                const uint32_t va = (uint32_t)(nm >> xa) & 1u, vb = (uint32_t)(nm >> xb) & 1u;
-                nb = (va << class_pos3<MT>(S, P, xa)) + (vb << class_pos3<MT>(S, P, xb));
-                // the old classes are read: move the neighbours' up-counts on
-                // the bit planes, sum the tallies, flip.  The barriers pin this
-                // vector order (scalar work may cross them): the plane update
-                // and the flip then sit in the waits of the DPP sum and of its
-                // read-back.  (Measured: 3 % off the dataflow sweep.)
-                planes_step_inv<MT>(P, nm, (MT)(int64_t)(int32_t)upm);
-                __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
-                nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
-                __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
-                if (on_row) S ^= bx;
-                __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
-            } else {
-                ym += ys == 0 ? wrapY : 0;
-                yp -= ys == By - 1 ? wrapY : 0;
-                xm += xs == 0 ? wrapX : 0;
-                xp -= xs == B - 1 ? wrapX : 0;
-                adj = (lane == ym || lane == yp) && lane < By;
-                const int ca = on_row ? xm : xs;
-                const bool va = on_row ? xm >= 0 : adj;
-                const bool vb = on_row && xp < B;
-                const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
-                const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
-                nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
-            }
-            uint32_t nb_s;
-            if (wrapY == 0) {  // rows ys -/+ 1 are the neighbouring lanes
-                if constexpr (WRAP) nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
-                nb_s = rdl32(nb, ys);
-            } else {
-                nb_s = rdl32(nb, ys) + rdl32(nb, ym) + rdl32(nb, yp);
-            }
-            // every neighbour moves one class up (flip to +1) or down: the
-            // whole tally shifts by one field (no class leaves its spin's range)
-            const uint32_t sub_s = nb_s + (1u << c3);
-            const uint32_t add_s =
-                (uint32_t)(((uint64_t)nb_s << 3) >> (upm & 6u)) + (1u << c3_new);
-            n_lane = n_lane + ((add_s >> lane3) & 7u) - ((sub_s >> lane3) & 7u);
-            ev_lane += lane == c ? 1u : 0u;
-            W = (double)n_lane * rd_lane;
-            Pinc = scan16_f64(W);
-            R = rdl_f64(Pinc, 9);
-
-            if constexpr (WRAP) {
-                // flip, and move the neighbours' up-counts on the bit planes
-                const MT bx = (MT)1 << xs;
-                const MT mrow = (xm >= 0 ? (MT)1 << xm : (MT)0) | (xp < B ? (MT)1 << xp : (MT)0);
-                nm = on_row ? mrow : (adj ? bx : (MT)0);
-                if (on_row) S ^= bx;
-                planes_step_inv<MT>(P, nm, (MT)(int64_t)(int32_t)upm);
-            }
-            pos = e + 1;
-            cand = __ballot(xh < R) & left;
+        // member j of class c in ascending row-major order: the row by a
+        // scan of per-row counts, the column by counting the row's
+        // members below each lane (mbcnt)
+        const MT cm = class_mask<MT>(class_sel(c), S, P, VM);
+        const uint32_t cnt = (uint32_t)popc(cm);
+        const uint32_t incl = sizeof(MT) == 4 ? scan32(cnt) : scan64(cnt);
+        const int ys = __builtin_ctzll(__ballot(incl > j));
+        const uint32_t jr = j - rdl32(incl - cnt, ys);
+        int xs;
+        if constexpr (sizeof(MT) == 8) {
+            const uint64_t row = rdl64(cm, ys);
+            xs = __builtin_ctzll(__ballot(bits_below_lane(row) == jr) & row);
+        } else {
+            const uint32_t row = rdl32(cm, ys);
+            xs = __builtin_ctzll(
+                __ballot(__builtin_amdgcn_mbcnt_lo(row, 0u) == jr) & (uint64_t)row);
         }
-        m_null += (uint32_t)__popcll(left);  // the batch's trailing nulls
-        // residence times -ln(u)/R of this batch's events, kept per lane
-        if (Rb != 0.0) {
+
+        // class changes of the flipped site and its in-tile neighbours as
+        // packed 3-bit per-class tallies (10 classes in 30 bits): row ys
+        // holds the sites at columns xs -/+ 1, rows ys -/+ 1 the site at
+        // column xs; the three rows are summed into row ys by DPP
+        // neighbour rows and columns; outside the tile (-1 or B) they are
+        // halo and frozen, unless the lattice is one periodic domain
+        // upm: all ones when the flipped spin is +1 (c >= 5), whose
+        // neighbours then lose an up neighbour; the flipped site moves
+        // to class c -/+ 5 (tally field 3 c -/+ 15)
+        const uint32_t upm = sgpr_sign_bit<0x3E0>((uint32_t)c);
+        const int c3 = 3 * c;
+        const int c3_new = c3 + 15 - (int)(upm & 30u);
+        const bool on_row = lane == ys;
+        constexpr int NB = 8 * (int)sizeof(MT);
+        int ym = ys - 1, yp = ys + 1, xm = xs - 1, xp = xs + 1;
+        bool adj;
+        MT nm = 0;    // this lane's neighbours of the flipped site
+        uint32_t nb;  // their classes as tallies
+        if constexpr (!WRAP) {
+            // row ys: columns xs -/+ 1 inside the tile; rows ys -/+ 1:
+            // column xs.  Each lane reads its sites at xa (xs - 1 on row
+            // ys, else xs) and xb = xs + 1; a column outside the tile, or
+            // not this lane's, is a clear bit of nm
+            const MT bx = (MT)1 << xs;
+            const MT mrow = ((bx << 1) | (bx >> 1)) & vm_row;
+            adj = (lane == ym || lane == yp) && lane < By;
+            nm = on_row ? mrow : (adj ? bx : (MT)0);
+            const int xa = (xs - (on_row ? 1 : 0)) & (NB - 1), xb = (xs + 1) & (NB - 1);
+            const uint32_t va = (uint32_t)(nm >> xa) & 1u, vb = (uint32_t)(nm >> xb) & 1u;
+            nb = (va << class_pos3<MT>(S, P, xa)) + (vb << class_pos3<MT>(S, P, xb));
+            // the old classes are read: move the neighbours' up-counts on
+            // the bit planes, sum the tallies, flip.  The barriers pin this
+            // vector order (scalar work may cross them): the plane update
+            // and the flip then sit in the waits of the DPP sum and of its
+            // read-back.  (Measured: 3 % off the dataflow sweep.)
+            planes_step_inv<MT>(P, nm, (MT)(int64_t)(int32_t)upm);
+            __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
+            nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
+            __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
+            if (on_row) S ^= bx;
+            __builtin_amdgcn_sched_barrier(kSchedScalarMayCross);
+        } else {
+            ym += ys == 0 ? wrapY : 0;
+            yp -= ys == By - 1 ? wrapY : 0;
+            xm += xs == 0 ? wrapX : 0;
+            xp -= xs == B - 1 ? wrapX : 0;
+            adj = (lane == ym || lane == yp) && lane < By;
+            const int ca = on_row ? xm : xs;
+            const bool va = on_row ? xm >= 0 : adj;
+            const bool vb = on_row && xp < B;
+            const uint32_t pa = class_pos3<MT>(S, P, ca & (NB - 1));
+            const uint32_t pb = class_pos3<MT>(S, P, xp & (NB - 1));
+            nb = ((va ? 1u : 0u) << pa) + ((vb ? 1u : 0u) << pb);
+        }
+        uint32_t nb_s;
+        if (wrapY == 0) {  // rows ys -/+ 1 are the neighbouring lanes
+            if constexpr (WRAP) nb += dppz<kWaveShr1>(nb) + dppz<kWaveShl1>(nb);
+            nb_s = rdl32(nb, ys);
+        } else {
+            nb_s = rdl32(nb, ys) + rdl32(nb, ym) + rdl32(nb, yp);
+        }
+        // every neighbour moves one class up (flip to +1) or down: the
+        // whole tally shifts by one field (no class leaves its spin's range)
+        const uint32_t sub_s = nb_s + (1u << c3);
+        const uint32_t add_s =
+            (uint32_t)(((uint64_t)nb_s << 3) >> (upm & 6u)) + (1u << c3_new);
+        n_lane = n_lane + ((add_s >> lane3) & 7u) - ((sub_s >> lane3) & 7u);
+        ev_lane += lane == c ? 1u : 0u;
+        W = (double)n_lane * rd_lane;
+        Pinc = scan16_f64(W);
+        R = rdl_f64(Pinc, 9);
+
+        if constexpr (WRAP) {
+            // flip, and move the neighbours' up-counts on the bit planes
+            const MT bx = (MT)1 << xs;
+            const MT mrow = (xm >= 0 ? (MT)1 << xm : (MT)0) | (xp < B ? (MT)1 << xp : (MT)0);
+            nm = on_row ? mrow : (adj ? bx : (MT)0);
+            if (on_row) S ^= bx;
+            planes_step_inv<MT>(P, nm, (MT)(int64_t)(int32_t)upm);
+        }
+    };
+
+    if constexpr (SLICE) {
+        // The rejection-free variant with fixed time slices: the domain's
+        // continuous-time kinetics run for rp.tau.  Event k takes Philox call
+        // (k, d | vis << 20 | kStreamSlice << 24, w, rho): words 3:2 give u
+        // and the waiting time dt = (-ln(u) 2^32) / R, words 1:0 a 64-bit
+        // word whose Lemire multiply by R (with rejection, redrawn on the
+        // slice retry streams) is x uniform on [0, R).  The visit ends at
+        // the first event whose time would pass tau, or at once when no
+        // event is possible (R = 0).  The calls of 64 events are drawn a
+        // batch at a time, one per lane; the logarithm is slice_log, whose
+        // sequence of IEEE operations is fixed, so every stop decision is
+        // reproducible.
+        const double tau = rp.tau;
+        const uint32_t cs = d | (vis << 20);
+        double tt = 0.0;
+        bool done = false;
+        for (uint32_t kb = 0; !done; kb += 64) {
+            const uint4 o = philox(kb + (uint32_t)lane, cs | (kStreamSlice << 24), w, rho, key0,
+                                   key1);
             const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
-            const double u = (double)(u53 + 1) * 0x1p-53;
-            neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / Rb);
+            const double nl = -slice_log((double)(u53 + 1) * 0x1p-53) * 4294967296.0;
+            const uint64_t word = ((uint64_t)o.y << 32) | o.x;
+            for (int l = 0; l < 64; ++l) {
+                if (R == 0.0) {
+                    done = true;
+                    break;
+                }
+                const double tn = tt + rdl_f64(nl, l) / R;
+                if (tn > tau) {
+                    done = true;
+                    break;
+                }
+                tt = tn;
+                const uint64_t Ru = (uint64_t)R;
+                uint64_t U = rdl64(word, l);
+                uint64_t lo = U * Ru;
+                if (lo < Ru) {  // rare: Lemire's threshold 2^64 mod R
+                    const uint64_t thr64 = (0 - Ru) % Ru;
+                    for (int r = 0; r < kMaxRetry && lo < thr64; ++r) {
+                        const uint4 o2 =
+                            philox(kb + (uint32_t)l, cs | ((kStreamSliceRetry0 + r) << 24), w,
+                                   rho, key0, key1);
+                        U = ((uint64_t)o2.y << 32) | o2.x;
+                        lo = U * Ru;
+                    }
+                }
+                event((double)__umul64hi(U, Ru) + 0.5);
+            }
+        }
+    } else {
+        for (int base = 0; base < NI; base += 64) {
+            const uint32_t t = (uint32_t)(base + lane);
+            const bool valid = base + lane < NI;
+            const uint4 o = philox(t, c1, w, rho, key0, key1);
+            uint64_t mm = (uint64_t)o.y * nd;
+            bool rej = valid && (uint32_t)mm < thr;
+            if (__ballot(rej)) {  // rare: redraw the slot on the retry streams
+                for (int k = 1; rej && k <= kMaxRetry; ++k) {
+                    const uint4 o2 =
+                        philox(t, d | (vis << 20) | ((kStreamRetry0 + k - 1) << 24), w,
+                               rho, key0, key1);
+                    mm = (uint64_t)o2.y * nd;
+                    rej = (uint32_t)mm < thr;
+                }
+            }
+            // x = slot 2^32 + w0, exact in a double, held as xh = x + 1/2: the
+            // comparisons with the integer sums R and P_c are unchanged by the
+            // half, and the member quotient below starts from it
+            const double xh = (double)(uint32_t)(mm >> 32) * 4294967296.0 + (double)o.x + 0.5;
+            uint64_t left = __ballot(valid);  // ticks of the batch not yet decided
+            double Rb = 0.0;                  // this lane's R before its event (0: none)
+            int pos = 0;
+            // the first undecided tick below R is the next event; the ticks
+            // before it are nulls
+            uint64_t cand = __ballot(xh < R) & left;
+            while (cand) {
+                const int e = __builtin_ctzll(cand);
+                left &= ~1ull << e;  // drop the ticks up to and including e
+                m_null += (uint32_t)(e - pos);
+                const double xe = rdl_f64(xh, e);  // x_e + 1/2
+                if (lane == e) Rb = R;
+
+                event(xe);
+                pos = e + 1;
+                cand = __ballot(xh < R) & left;
+            }
+            m_null += (uint32_t)__popcll(left);  // the batch's trailing nulls
+            // residence times -ln(u)/R of this batch's events, kept per lane
+            if (Rb != 0.0) {
+                const uint64_t u53 = ((uint64_t)o.w << 21) | (o.z >> 11);
+                const double u = (double)(u53 + 1) * 0x1p-53;
+                neumaier_add(clk_sum, clk_comp, -log(u) * 4294967296.0 / Rb);
+            }
         }
     }
     if constexpr (SCORE) {
@@ -967,8 +1070,12 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         cc = wave_sum_f64(cc);
         if (lane == 0) {
             double ds = dom->clk_sum, dc = dom->clk_comp;
-            neumaier_add(ds, dc, cs);
-            neumaier_add(ds, dc, cc);
+            if constexpr (SLICE) {
+                neumaier_add(ds, dc, rp.tau);  // the domain's clock: one slice
+            } else {
+                neumaier_add(ds, dc, cs);
+                neumaier_add(ds, dc, cc);
+            }
             dom->clk_sum = ds;
             dom->clk_comp = dc;
             dom->events += out.events;
@@ -1033,7 +1140,7 @@ __device__ inline double replica_time(const KParams &K, const Rep &rp, int lane)
 
 // Phase p of the current sweep: one wavefront per (replica, domain of the
 // phase's colour).  Launched once per phase; domains of a colour commute.
-template <typename MT, bool SCORE, bool WRAP>
+template <typename MT, bool SCORE, bool WRAP, bool SLICE = false>
 __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
     const int task = K.task_begin + (int)blockIdx.x;
@@ -1045,7 +1152,7 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     if (col < 0 || task - rp.task_off >= domains_of_colour(rp, col)) return;
     int d, oy, ox;
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
-    const VisitOut o = visit_domain<MT, SCORE, WRAP>(
+    const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
         (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
     if (__lane_id() == 0) {
@@ -1098,7 +1205,7 @@ constexpr int kFlowMaxSweeps = 64;  // sweeps of one dataflow launch
 // can hang.  Sweeps overlap, so a visit adds its
 // changes of M, B and events to its sweep's slot and stores its domain's
 // clock after the sweep's last visit; k_flow_close forms the records.
-template <typename MT, bool SCORE, bool WRAP>
+template <typename MT, bool SCORE, bool WRAP, bool SLICE = false>
 __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase,
                                              int64_t *done) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPerWave];
@@ -1155,7 +1262,7 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
     }
     __builtin_amdgcn_wave_barrier();
     Dom *dm = K.dom + rp.dom_off + d;
-    const VisitOut o = visit_domain<MT, SCORE, WRAP>(
+    const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
         (uint32_t)vis, w, (uint32_t)rho, K.seed, dm, lds);
     if (__lane_id() == 0) {
@@ -1325,7 +1432,7 @@ struct TeamShared {
 // the workgroup).  In each colour phase wavefront `wave` takes the phase's
 // domains wave, wave + nw, ...; with a team a workgroup barrier separates the
 // phases (domains of one colour never touch, so the split changes no result).
-template <typename MT, bool SCORE, bool WRAP>
+template <typename MT, bool SCORE, bool WRAP, bool SLICE = false>
 __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lane,
                             uint8_t *lds, TeamShared *ts, int64_t sweep0,
                             int64_t run_done0, int64_t n_sweeps, int64_t rec_every,
@@ -1344,7 +1451,7 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
             for (int i2 = wave; i2 < per_colour; i2 += nw) {
                 int d, oy, ox;
                 colour_domain(rp, col, i2, &d, &oy, &ox);
-                const VisitOut o = visit_domain<MT, SCORE, WRAP>(
+                const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
                     K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
                     (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
                 dM += o.dM;
@@ -1397,7 +1504,7 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
 // a whole workgroup (costliest first), then n_solo replicas run by single
 // wavefronts (costliest first).  Every wavefront leaves once both queues
 // are drained.  One call site keeps the domain process inlined once.
-template <typename MT, bool SCORE, bool WRAP>
+template <typename MT, bool SCORE, bool WRAP, bool SLICE = false>
 __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
     KParams K, int64_t n_sweeps) {
     __shared__ __attribute__((aligned(16)))
@@ -1443,7 +1550,7 @@ __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
         rho = __builtin_amdgcn_readfirstlane(rho);
         me = __builtin_amdgcn_readfirstlane(me);
         nw = __builtin_amdgcn_readfirstlane(nw);
-        run_replica<MT, SCORE, WRAP>(K, rho, me, nw, lane, lds, &ts, sweep0, run_done0, n_sweeps,
+        run_replica<MT, SCORE, WRAP, SLICE>(K, rho, me, nw, lane, lds, &ts, sweep0, run_done0, n_sweeps,
                                rec_every, rec_base);
     }
 }

@@ -39,7 +39,7 @@ class ReplicaDesc(C.Structure):
     _fields_ = [("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
                 ("L", C.c_int32), ("tile", C.c_int32), ("steps_per_visit", C.c_int32),
                 ("rate_model", C.c_int32), ("schedule", C.c_int32), ("init", C.c_int32),
-                ("tile_rows", C.c_int32), ("dims", C.c_int32)]
+                ("tile_rows", C.c_int32), ("dims", C.c_int32), ("time_slice", C.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("sweep", "<i8"), ("M", "<i8"), ("B", "<i8"),
@@ -148,7 +148,8 @@ def make_descs(descs):
                              int(d.get("schedule", SCHED_RANDOM_PERM)),
                              int(d.get("init", INIT_RANDOM)),
                              int(d.get("tile_rows", 0)),
-                             int(d.get("dims", 0)))
+                             int(d.get("dims", 0)),
+                             float(d.get("time_slice", 0.0)))
     return arr
 
 
@@ -192,7 +193,8 @@ def kmc_exact_sweeps_static(desc, p, n_sweeps, quantised=True, stream=None):
 def kmc_init_lattice(descs, seed, given_spins=None, stream=None):
     """descs: list of dicts with keys L, tile, T and optional J, h,
     steps_per_visit, rate_model, schedule, init, tile_rows (domain height;
-    0 or absent: square domains), dims (1: a ring of L sites).  stream: a hipStream_t
+    0 or absent: square domains), dims (1: a ring of L sites), time_slice
+    (> 0: the rejection-free variant with fixed time slices).  stream: a hipStream_t
     handle (int) or None for torch's current stream.  Returns the context."""
     arr = make_descs(descs)
     if stream is None:

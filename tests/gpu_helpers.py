@@ -19,7 +19,8 @@ def oracle_for(kmco, desc, seed, rho, spins=None):
                         rate_model=desc.get("rate_model", 0),
                         schedule=desc.get("schedule", 0), init=desc.get("init", 0),
                         seed=seed, replica=rho, spins=spins,
-                        tile_rows=desc.get("tile_rows", 0), dims=desc.get("dims", 2) or 2)
+                        tile_rows=desc.get("tile_rows", 0), dims=desc.get("dims", 2) or 2,
+                        time_slice=desc.get("time_slice", 0.0))
 
 
 def assert_records_equal(gpu, ora, what=""):

@@ -140,12 +140,15 @@ def test_header_compiles_as_plain_c(tmp_path):
     src = tmp_path / "use.c"
     src.write_text(
         '#include "kmc.h"\n'
+        "#include <stddef.h>\n"
         "int main(void) {\n"
         "    kmc_rate_model m = KMC_RATE_BARKER;\n"
         "    kmc_schedule s = KMC_SCHED_PALINDROME;\n"
         "    kmc_init i = KMC_INIT_ALL_UP;\n"
         "    kmc_replica_desc d = {0};\n"
         "    kmc_record r = {0};\n"
+        "    _Static_assert(sizeof(kmc_replica_desc) == 64, \"descriptor size\");\n"
+        "    _Static_assert(offsetof(kmc_replica_desc, time_slice) == 56, \"slice\");\n"
         "    kmc_status (*f)(kmc_ctx *, int32_t, double *, double *) = kmc_get_domain_clocks;\n"
         "    (void)d; (void)r; (void)f;\n"
         "    return (int)m + (int)s + (int)i - 3;\n"
@@ -155,3 +158,19 @@ def test_header_compiles_as_plain_c(tmp_path):
                     os.path.join(ROOT, "include"), str(src), "-o", str(exe) + ".o"],
                    check=True)
 
+
+
+def test_descriptor_layout(kmc):
+    """The descriptor as the C header lays it out (64 bytes: three doubles,
+    eight int32 fields, the time slice), and refusals that need no GPU."""
+    import ctypes
+    assert ctypes.sizeof(kmc.ReplicaDesc) == 64
+    assert kmc.ReplicaDesc.time_slice.offset == 56 and kmc.ReplicaDesc.dims.offset == 52
+    L = kmc.lib()
+    p = C.c_void_p(16)
+    sl = kmc.make_descs([dict(L=4, tile=2, T=2.0, time_slice=0.5)])
+    assert L.kmc_exact_sweeps(sl, p, p, 1, 0, None) == kmc.KMC_EUNSUPPORTED
+    neg = kmc.make_descs([dict(L=4, tile=2, T=2.0, time_slice=-1.0)])
+    assert L.kmc_exact_sweeps(neg, p, p, 1, 0, None) == kmc.KMC_EINVAL
+    ring = kmc.make_descs([dict(L=8, tile=3, T=2.0, dims=1)])   # 8 % 3 != 0
+    assert L.kmc_exact_sweeps(ring, p, p, 1, 0, None) == kmc.KMC_EINVAL
