@@ -57,10 +57,18 @@ HBM_PEAK = 8.0e12
 # summaries in profiles/ name the command).  Valid only for the kernel source
 # the counters were taken on (sha256 of kmc_device.h); null otherwise.
 TRAFFIC = {
-    "kernel_source_sha256": None,
+    "kernel_source_sha256": "b6796d35f870a06446418e264bb4fde3b99f160c0b4af6505a8f00eaee4a81ce",
     "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
     # workload -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per sweep
-    "kib_per_sweep": {},
+    "kib_per_sweep": {
+        # profiles/k_flow_ising2d_L1024_tile32_plain.md
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (216655.38 / 64, 77950.31 / 64),
+        # profiles/k_flow_ising2d_L1024_tile32_small_NI.md
+        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (221462.25 / 64, 78941.06 / 64),
+        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (220025.56 / 64, 77164.34 / 64),
+        # profiles/k_flow_ising2d_L4096_tile64_quench.md
+        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (166706.50 / 8, 137407.84 / 8),
+    },
 }
 
 
@@ -368,6 +376,8 @@ def main():
                     help="all: the full line; the others run one part (for profiling)")
     ap.add_argument("--ni", type=int, default=0,
                     help="--mode small_ni: run only this N_I (default: 1, 2, 5, 10)")
+    ap.add_argument("--L", type=int, default=1024, choices=[1024, 4096],
+                    help="--mode small_ni: the 1024^2 lattice or the 4096^2 one")
     ap.add_argument("--no-extras", action="store_true", help="same as --mode plain")
     ap.add_argument("--tiles", default="", help="batched workload tiles, e.g. 16:8,24:12")
     ap.add_argument("--flags", type=int, default=0, help="extra kmc_run_schedule flags (batched)")
@@ -404,8 +414,13 @@ def main():
         print(json.dumps({"backward": g}), flush=True)
         return
     if args.mode == "small_ni":
+        if args.L == 4096:
+            seed3, d3s, _ = workloads.quench_4096()
+            d, sd = d3s[0], seed3
+        else:
+            d, sd = d2, seed2
         for ni in ([args.ni] if args.ni else SMALL_NI):
-            p = plain(args, kmc, small_ni_desc(d2, ni), seed2, args.steps, args.warmup)
+            p = plain(args, kmc, small_ni_desc(d, ni), sd, args.steps, args.warmup)
             print(json.dumps({f"NI{ni}": leg(p)}), flush=True)
         return
     if args.mode == "quench":
@@ -470,6 +485,10 @@ def main():
         for ni in SMALL_NI:
             line["small_NI"][f"NI{ni}"] = leg(
                 plain(args, kmc, small_ni_desc(d2, ni), seed2, 3 * kmc.FLOW_MAX_SWEEPS, 16))
+        # the same visit length on the 4096^2 lattice: 16 times the visits per
+        # sweep for the same dependency depth of the schedule
+        line["small_NI"]["NI10_L4096"] = leg(
+            plain(args, kmc, small_ni_desc(d3s[0], 10), seed3, 64, 16))
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
         b_ops = OPS_PER_TICK * b["ticks"] + OPS_PER_EVENT * b["events"]

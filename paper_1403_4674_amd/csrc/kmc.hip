@@ -561,10 +561,14 @@ void launch_resident(kmc_ctx *c, KParams K, int64_t n_sweeps) {
 
 // Per-sweep slots of the dataflow launches, allocated once (captured graphs
 // keep their addresses).
+// (Each buffer is checked on its own: after a failed allocation the next
+// call allocates what is still missing.)
 void ensure_flow_slots(kmc_ctx *c) {
-    if (c->d_flow_acc) return;
-    c->d_flow_acc = alloc_n<int64_t>(c, (int64_t)kmcdev::kFlowMaxSweeps * c->n_rep * 3);
-    c->d_flow_clk = alloc_n<double>(c, (int64_t)kmcdev::kFlowMaxSweeps * std::max(c->n_dom, 1) * 2);
+    if (!c->d_flow_acc)
+        c->d_flow_acc = alloc_n<int64_t>(c, (int64_t)kmcdev::kFlowMaxSweeps * c->n_rep * 3);
+    if (!c->d_flow_clk)
+        c->d_flow_clk =
+            alloc_n<double>(c, (int64_t)kmcdev::kFlowMaxSweeps * std::max(c->n_dom, 1) * 2);
 }
 
 void ensure_records(kmc_ctx *c, int64_t need) {
@@ -590,10 +594,11 @@ void ensure_records(kmc_ctx *c, int64_t need) {
 }
 
 void ensure_bins(kmc_ctx *c, int64_t n_bins) {
-    if (n_bins <= c->bins_cap) return;
+    if (n_bins <= c->bins_cap && c->d_bins) return;
     hip_check(c, hipStreamSynchronize(c->stream), "bins sync");
     dev_free(c, c->d_bins);
     c->d_bins = nullptr;
+    c->bins_cap = 0;  // stays 0 if the allocation below fails
     c->d_bins = alloc_n<double>(c, n_bins * c->n_rep * 2);
     c->bins_cap = n_bins;
 }
@@ -1198,13 +1203,20 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
                 fail(c, KMC_EUNSUPPORTED, "one dataflow sweep exceeds the launch grid limit");
         }
         if (n_sweeps == 0) return KMC_OK;
+        // every buffer the run needs is allocated before anything is
+        // enqueued or any state changes: a failed allocation (KMC_ENOMEM)
+        // leaves the context as it was
+        const bool score = (flags & KMC_F_SCORE) != 0;
+        const int64_t n_bins = (n_sweeps + record_every - 1) / record_every;
         ensure_records(c, c->n_rec + n_sweeps / record_every);
         if (flags & KMC_F_CHECKPOINT) {
-            if (!c->c_spins) {
-                c->c_spins = alloc_n<int8_t>(c, c->spin_bytes);
-                c->c_dom = alloc_n<Dom>(c, c->n_dom);
-                c->c_acc = alloc_n<RepAcc>(c, c->n_rep);
-            }
+            if (!c->c_spins) c->c_spins = alloc_n<int8_t>(c, c->spin_bytes);
+            if (!c->c_dom) c->c_dom = alloc_n<Dom>(c, c->n_dom);
+            if (!c->c_acc) c->c_acc = alloc_n<RepAcc>(c, c->n_rep);
+        }
+        if (flags & KMC_F_FLOW) ensure_flow_slots(c);
+        if (score) ensure_bins(c, n_bins);
+        if (flags & KMC_F_CHECKPOINT) {
             hip_check(c, hipMemcpyAsync(c->c_spins, c->d_spins, c->spin_bytes,
                                         hipMemcpyDeviceToDevice, c->stream), "checkpoint");
             hip_check(c, hipMemcpyAsync(c->c_dom, c->d_dom, sizeof(Dom) * c->n_dom,
@@ -1220,18 +1232,14 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         c->timing = (flags & KMC_F_TIMING) != 0;
         c->flow = (flags & KMC_F_FLOW) != 0;
         if (c->flow) {
-            ensure_flow_slots(c);
             // counters restart with every run (a replay may go back in sweeps)
             hipLaunchKernelGGL(kmcdev::k_fill_i64, dim3((unsigned)((c->n_dom + 255) / 256)),
                                dim3(256), 0, c->stream, c->d_done, (int64_t)c->n_dom,
                                (int64_t)0);
         }
         KParams K = params(c);
-        const bool score = (flags & KMC_F_SCORE) != 0;
         if (score || (flags & KMC_F_CHECKPOINT)) c->fused_score = false;
         if (score) {
-            const int64_t n_bins = (n_sweeps + record_every - 1) / record_every;
-            ensure_bins(c, n_bins);
             const int64_t nb = n_bins * c->n_rep * 2;
             hipLaunchKernelGGL(kmcdev::k_fill_f64, dim3((unsigned)((nb + 255) / 256)),
                                dim3(256), 0, c->stream, c->d_bins, nb, 0.0);
@@ -1331,13 +1339,12 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         const int64_t n_bins = (c->ck_n_sweeps + c->ck_rec_every - 1) / c->ck_rec_every;
         if (!score || capacity < n_bins)
             fail(c, KMC_EINVAL, "score buffer smaller than the number of intervals");
-        if (!c->r_spins) {
-            c->r_spins = alloc_n<int8_t>(c, c->spin_bytes);
-            c->r_dom = alloc_n<Dom>(c, c->n_dom);
-            c->r_acc = alloc_n<RepAcc>(c, c->n_rep);
-            c->r_ctl = alloc_n<Ctl>(c, 1);
-        }
+        if (!c->r_spins) c->r_spins = alloc_n<int8_t>(c, c->spin_bytes);
+        if (!c->r_dom) c->r_dom = alloc_n<Dom>(c, c->n_dom);
+        if (!c->r_acc) c->r_acc = alloc_n<RepAcc>(c, c->n_rep);
+        if (!c->r_ctl) c->r_ctl = alloc_n<Ctl>(c, 1);
         ensure_bins(c, n_bins);
+        if (c->ck_flags & KMC_F_FLOW) ensure_flow_slots(c);
         hipStream_t s = c->stream;
         hip_check(c, hipMemcpyAsync(c->r_spins, c->c_spins, c->spin_bytes,
                                     hipMemcpyDeviceToDevice, s), "replay copy");
