@@ -62,12 +62,12 @@ TRAFFIC = {
     # workload -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per sweep
     "kib_per_sweep": {
         # profiles/k_flow_ising2d_L1024_tile32_plain.md
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (216655.38 / 64, 77950.31 / 64),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (216423.88 / 64, 77937.25 / 64),
         # profiles/k_flow_ising2d_L1024_tile32_small_NI.md
-        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (221462.25 / 64, 78941.06 / 64),
-        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (220025.56 / 64, 77164.34 / 64),
+        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (218167.56 / 64, 78843.44 / 64),
+        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (221381.38 / 64, 77146.59 / 64),
         # profiles/k_flow_ising2d_L4096_tile64_quench.md
-        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (166706.50 / 8, 137407.84 / 8),
+        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (166413.44 / 8, 137447.41 / 8),
     },
 }
 
