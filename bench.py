@@ -50,24 +50,27 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # MI355X HBM3E
 HBM_PEAK = 8.0e12
 
-# HBM bytes per sweep of the plain-form kernels on each plain workload:
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, divided by
-# the sweeps of the dispatch), each scaled by what the counter reads for a
-# 1 GiB device copy (profiles/copy_calibration_1GiB.md; the per-workload
-# summaries in profiles/ name the command).  Valid only for the kernel source
-# the counters were taken on (sha256 of kmc_device.h); null otherwise.
+# HBM bytes per sweep of the plain-form kernels on each plain workload, from
+# rocprofv3 counters of the timed dispatch divided by its sweeps: reads are
+# 32 n32 + 64 n64 + 128 n128 over the L2-to-memory read requests of each
+# size (TCC_EA0_RDREQ_32B/64B/128B_sum; FETCH_SIZE counts a 128-byte request
+# as 64 bytes on this GPU), writes are WRITE_SIZE (KiB).  On a 1 GiB device
+# copy both give 1 GiB (profiles/copy_calibration_1GiB.md; the per-workload
+# summaries in profiles/ name the commands).  Valid only for the kernel
+# source the counters were taken on (sha256 of kmc_device.h); null otherwise.
 TRAFFIC = {
-    "kernel_source_sha256": "b6796d35f870a06446418e264bb4fde3b99f160c0b4af6505a8f00eaee4a81ce",
-    "fetch_scale": 1048576.0 / 524308.0, "write_scale": 1048576.0 / 1048576.0,
-    # workload -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per sweep
-    "kib_per_sweep": {
+    "kernel_source_sha256": "fe73ada48ae3f4dc47edcb9b8f17a1d38858a1394ad771c5f9e338f26ffd1740",
+    # workload -> (read bytes, WRITE_SIZE KiB) per sweep
+    "per_sweep": {
         # profiles/k_flow_ising2d_L1024_tile32_plain.md
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (216423.88 / 64, 77937.25 / 64),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (53882624 / 64, 80041.16 / 64),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain_phased": (4 * 493.303 * 1024,
+                                                                       4 * 296.0),
         # profiles/k_flow_ising2d_L1024_tile32_small_NI.md
-        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (218167.56 / 64, 78843.44 / 64),
-        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (221381.38 / 64, 77146.59 / 64),
+        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (52461440 / 64, 81016.91 / 64),
+        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (52229952 / 64, 79357.78 / 64),
         # profiles/k_flow_ising2d_L4096_tile64_quench.md
-        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (166413.44 / 8, 137447.41 / 8),
+        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (41741440 / 8, 138381.22 / 8),
     },
 }
 
@@ -82,10 +85,10 @@ def kernel_source_sha():
 def traffic_per_sweep(workload):
     """Calibrated HBM bytes per sweep measured for `workload`, or None."""
     t = TRAFFIC
-    if workload not in t["kib_per_sweep"] or t["kernel_source_sha256"] != kernel_source_sha():
+    if workload not in t["per_sweep"] or t["kernel_source_sha256"] != kernel_source_sha():
         return None
-    fetch, write = t["kib_per_sweep"][workload]
-    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+    read, write_kib = t["per_sweep"][workload]
+    return read + write_kib * 1024.0
 
 
 def ticks_per_sweep(d):

@@ -82,7 +82,9 @@ struct kmc_ctx {
 
     Rep *d_reps = nullptr;
     Rates *d_rates = nullptr;
-    int8_t *d_spins = nullptr;
+    int8_t *d_spins = nullptr;   // every replica's lattice, domain by domain
+    uint64_t *d_edges = nullptr; // edge columns of every domain [n_dom][2]
+    int8_t *d_stage = nullptr;   // one row-major lattice (given starts, copies out)
     Dom *d_dom = nullptr;
     RepAcc *d_acc = nullptr;
     Record *d_rec = nullptr;
@@ -113,6 +115,7 @@ struct kmc_ctx {
 
     // replay buffers of kmc_backward_score
     int8_t *r_spins = nullptr;
+    uint64_t *r_edges = nullptr;
     Dom *r_dom = nullptr;
     RepAcc *r_acc = nullptr;
     Ctl *r_ctl = nullptr;
@@ -341,6 +344,7 @@ KParams params(kmc_ctx *c) {
     K.flow_clk = c->d_flow_clk;
     K.n_dom_total = c->n_dom;
     K.flow_max_polls = c->flow_max_polls;
+    K.edges = c->d_edges;
     return K;
 }
 
@@ -677,6 +681,16 @@ int64_t bytes_of_spins(const kmc_replica_desc &d) { return (int64_t)d.L * rows_o
 // dependency never satisfied): the results of the run are not valid.
 // A dataflow wait that gave up leaves the flag set for good: visits after
 // it may have read a halo out of order, so the context's results are void.
+// Rebuild the edge columns of every domain of K.spins into K.edges (before a
+// run of the staged visits, which read and keep them).
+void rebuild_edges(kmc_ctx *c, const KParams &K) {
+    int most = 1;
+    for (const Rep &rp : c->reps) most = std::max(most, rp.ND);
+    hipLaunchKernelGGL(kmcdev::k_edges, dim3((unsigned)((most + 255) / 256), c->n_rep),
+                       dim3(256), 0, c->stream, K);
+    launch_check(c, "edge columns");
+}
+
 void check_flow_error(kmc_ctx *c, const Ctl *ctl) {
     Ctl h;
     hip_check(c, hipMemcpy(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "ctl copy");
@@ -692,7 +706,8 @@ void destroy_buffers(kmc_ctx *c) {
                     c->d_rec,   c->d_ctl,   c->d_task_rep, c->d_order, c->c_spins,
                     c->c_dom,   c->c_acc,   c->r_spins, c->r_dom,   c->r_acc,
                     c->r_ctl,   c->d_bins,  c->d_tmp_rec, c->d_order_nm, c->d_items,
-                    c->d_done, c->d_flow_acc, c->d_flow_clk};
+                    c->d_done, c->d_flow_acc, c->d_flow_clk, c->d_edges, c->d_stage,
+                    c->r_edges};
     for (void *p : bufs) dev_free(c, p);
 }
 
@@ -1084,6 +1099,12 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         c->d_reps = alloc_n<Rep>(c, n_rep);
         c->d_rates = alloc_n<Rates>(c, n_rep);
         c->d_spins = alloc_n<int8_t>(c, off);
+        c->d_edges = alloc_n<uint64_t>(c, 2 * (int64_t)std::max(dom, 1));
+        {
+            int64_t most = 1;
+            for (auto &q : c->desc) most = std::max(most, bytes_of_spins(q));
+            c->d_stage = alloc_n<int8_t>(c, most);
+        }
         c->d_dom = alloc_n<Dom>(c, dom);
         c->d_acc = alloc_n<RepAcc>(c, n_rep);
         c->d_ctl = alloc_n<Ctl>(c, 1);
@@ -1113,7 +1134,10 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
         hip_check(c, hipMemsetAsync(c->d_ctl, 0, sizeof(Ctl), s), "zero");
         hip_check(c, hipMemsetAsync(c->d_done, 0, sizeof(int64_t) * std::max(dom, 1), s),
                   "zero");
+        KParams K = params(c);
         if (any_given) {
+            // row-major in, domain by domain on the device (the staging
+            // lattice is reused in stream order)
             int64_t src = 0;
             for (int rho = 0; rho < n_rep; ++rho) {
                 const int64_t nb = bytes_of_spins(d[rho]);
@@ -1121,17 +1145,19 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                     for (int64_t i = 0; i < nb; ++i)
                         if (given_spins[src + i] != 1 && given_spins[src + i] != -1)
                             fail(c, KMC_EINVAL, "given spins must be +1 or -1");
-                    hip_check(c, hipMemcpyAsync(c->d_spins + c->reps[rho].spin_off,
-                                                given_spins + src, nb,
+                    hip_check(c, hipMemcpyAsync(c->d_stage, given_spins + src, nb,
                                                 hipMemcpyHostToDevice, s),
                               "copy given spins");
+                    hipLaunchKernelGGL(kmcdev::k_spins_layout<true>,
+                                       dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, K,
+                                       rho, c->d_stage);
+                    launch_check(c, "given spins");
                 }
                 src += nb;
             }
         }
         int maxL = 0;
         for (auto &q : c->desc) maxL = std::max(maxL, q.L);
-        KParams K = params(c);
         const int64_t maxN = (int64_t)maxL * maxL;
         hipLaunchKernelGGL(kmcdev::k_init_spins,
                            dim3((unsigned)((maxN / 128 + 255) / 256 + 1), n_rep), dim3(256),
@@ -1248,6 +1274,7 @@ extern "C" kmc_status kmc_run_schedule(kmc_ctx *c, int64_t n_sweeps, int32_t rec
         }
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, c->stream, c->d_ctl,
                            (int64_t)0, c->n_rec, (int64_t)record_every, c->sweep);
+        if (!(flags & KMC_F_RESIDENT)) rebuild_edges(c, K);
         if (flags & KMC_F_RESIDENT) {
             if (score)
                 launch_resident<true>(c, K, n_sweeps);
@@ -1340,6 +1367,7 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         if (!score || capacity < n_bins)
             fail(c, KMC_EINVAL, "score buffer smaller than the number of intervals");
         if (!c->r_spins) c->r_spins = alloc_n<int8_t>(c, c->spin_bytes);
+        if (!c->r_edges) c->r_edges = alloc_n<uint64_t>(c, 2 * (int64_t)std::max(c->n_dom, 1));
         if (!c->r_dom) c->r_dom = alloc_n<Dom>(c, c->n_dom);
         if (!c->r_acc) c->r_acc = alloc_n<RepAcc>(c, c->n_rep);
         if (!c->r_ctl) c->r_ctl = alloc_n<Ctl>(c, 1);
@@ -1357,6 +1385,7 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
                            0, s, c->d_bins, nb, 0.0);
         KParams K = params(c);
         K.spins = c->r_spins;
+        K.edges = c->r_edges;
         K.dom = c->r_dom;
         K.acc = c->r_acc;
         K.ctl = c->r_ctl;
@@ -1367,6 +1396,7 @@ extern "C" kmc_status kmc_backward_score(kmc_ctx *c, double *score, int64_t capa
         hip_check(c, hipMemsetAsync(c->r_ctl, 0, sizeof(Ctl), s), "replay ctl");
         hipLaunchKernelGGL(kmcdev::k_set_ctl, dim3(1), dim3(1), 0, s, c->r_ctl, (int64_t)0,
                            (int64_t)0, (int64_t)c->ck_rec_every, c->ck_sweep);
+        if (!(c->ck_flags & KMC_F_RESIDENT)) rebuild_edges(c, K);
         if (c->ck_flags & KMC_F_RESIDENT) {
             launch_resident<true>(c, K, c->ck_n_sweeps);
         } else if (c->ck_flags & KMC_F_PERSISTENT) {
@@ -1402,9 +1432,13 @@ extern "C" kmc_status kmc_get_spins(kmc_ctx *c, int32_t replica, int8_t *out) {
     }
     try {
         const Rep &rp = c->reps[replica];
-        hip_check(c, hipMemcpyAsync(out, c->d_spins + rp.spin_off,
-                                    (size_t)kmcdev::lattice_sites(rp),
-                                    hipMemcpyDeviceToHost, c->stream), "spin copy");
+        const int64_t n = kmcdev::lattice_sites(rp);
+        // domain by domain on the device, row-major out
+        hipLaunchKernelGGL(kmcdev::k_spins_layout<false>, dim3((unsigned)((n + 255) / 256)),
+                           dim3(256), 0, c->stream, params(c), replica, c->d_stage);
+        launch_check(c, "spin layout");
+        hip_check(c, hipMemcpyAsync(out, c->d_stage, (size_t)n, hipMemcpyDeviceToHost,
+                                    c->stream), "spin copy");
         hip_check(c, hipStreamSynchronize(c->stream), "spin sync");
         check_flow_error(c, c->d_ctl);
     } catch (const Fail &f) {

@@ -81,6 +81,27 @@ __device__ __host__ __forceinline__ int64_t lattice_sites(const Rep &rp) {
     return rp.z == 2 ? (int64_t)rp.L : (int64_t)rp.L * rp.L;
 }
 
+// Spins in HBM are held domain by domain: domain d = ty NT + tx owns the
+// bytes [d n_d, (d + 1) n_d) of its replica's block, its By rows of Bx sites
+// in order.  A visit's tile is then one contiguous run of whole memory
+// sectors, and so is the row of a neighbouring domain that forms a halo row.
+// (On the ring, and with one domain across, this is the plain row-major
+// order.)  Only the kernels see this order: spins enter and leave the
+// library row-major.
+__device__ __host__ __forceinline__ int64_t site_offset(const Rep &rp, int y, int x) {
+    const int ty = y / rp.By, tx = x / rp.B;
+    return ((int64_t)(ty * rp.NT + tx) * rp.By + (y - ty * rp.By)) * rp.B + (x - tx * rp.B);
+}
+
+// The inverse: row-major index y L + x of the site at byte j of the block.
+__device__ __host__ __forceinline__ int64_t row_major_of(const Rep &rp, int64_t j) {
+    const int nd = (int)rp.nd;
+    const int dd = (int)(j / nd), k = (int)(j - (int64_t)dd * nd);
+    const int r = k / rp.B, c = k - r * rp.B;
+    const int ty = dd / rp.NT, tx = dd - ty * rp.NT;
+    return (int64_t)(ty * rp.By + r) * rp.L + tx * rp.B + c;
+}
+
 struct Dom {
     double clk_sum, clk_comp;  // compensated event clock
     int64_t events;
@@ -131,6 +152,11 @@ struct KParams {
     double *flow_clk;
     int32_t n_dom_total;      // domain records of all replicas
     int64_t flow_max_polls;   // bound of each wait of the dataflow sweeps
+    // edge columns of every domain as row bit masks [domain record][2]: its
+    // first (x = ox) and last (x = ox + Bx - 1) column, bit r = row r.
+    // Rebuilt from the spins before each run of the staged visits and kept
+    // by them, so a visit reads its left and right halo as two words.
+    uint64_t *edges;
 };
 
 // ------------------------------------------------------------------ Philox
@@ -701,8 +727,11 @@ struct VisitOut {
 };
 
 // One domain process: N_I ticks of domain d (origin oy, ox) of the lattice
-// `lat` (side L, domain side B).  Executed by one full wavefront; `lds`
-// points at this wavefront's kLdsPerWave bytes.  The domain's compensated
+// `lat` (side L, domains Bx x By, held domain by domain).  Executed by one
+// full wavefront; `lds` points at this wavefront's kLdsPerWave bytes.
+// `edges` is the replica's edge-column table (two row masks per domain): the
+// left and right halo are read from the neighbours' entries, and the
+// domain's own entry is rewritten with the tile.  The domain's compensated
 // clock in *dom is advanced; the changes of M, B and the event count are
 // returned (and the score when SCORE).  WRAP admits replicas whose lattice
 // is a single periodic domain; without it the wrap-around bookkeeping is
@@ -713,53 +742,64 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
                                  const Rates *__restrict__ rt, int oy, int ox,
                                  uint32_t d, uint32_t vis, uint32_t w,
                                  uint32_t rho, uint64_t seed, Dom *dom,
-                                 uint8_t *lds) {
+                                 uint64_t *edges, uint8_t *lds) {
     const int lane = __lane_id();
     // B: row width (bits of a row mask), By: rows (lanes)
-    const int L = rp.L, B = rp.B, By = rp.By, NI = rp.NI;
+    const int B = rp.B, By = rp.By, NI = rp.NI;
     const int B4 = B >> 2;
     const uint32_t nd = rp.nd, thr = rp.thr;
 
+    // neighbouring domains (periodic), from the origin: no division
+    const int NT = rp.NT, NTy = rp.NTy;
+    const int dd = (int)d;
+    const int d_up = oy == 0 ? dd + (NTy - 1) * NT : dd - NT;
+    const int d_dn = oy + By == By * NTy ? dd - (NTy - 1) * NT : dd + NT;
+    const int d_lf = ox == 0 ? dd + NT - 1 : dd - 1;
+    const int d_rt = ox + B == B * NT ? dd - (NT - 1) : dd + 1;
+
     // ---- stage the tile and the top/bottom halo rows through LDS.  LDS rows
-    // are padded to whole dwords (stride SB); widths that are multiples of 4
-    // move as dwords, other widths byte by byte.
+    // are padded to whole dwords (stride SB).  With widths that are multiples
+    // of 4 the LDS tile is the HBM tile byte for byte and moves in 16-byte
+    // (else 4-byte) pieces; other widths move byte by byte.
     const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds;
     uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
+    const int8_t *blk = lat + (int64_t)dd * (int)nd;
+    const int8_t *up_row = lat + (int64_t)d_up * (int)nd + (By - 1) * B;  // its last row
+    const int8_t *dn_row = lat + (int64_t)d_dn * (int)nd;                 // its first row
     // the ring (one row of L sites) has no rows above and below: its domains
     // have no top and bottom halo, and those neighbours count as down
     const bool ring = rp.z == 2;
     if ((B & 3) == 0) {
-        for (int q = lane; q < By * B4; q += 64) {
-            const int row = q / B4, c4 = q - row * B4;
-            const uint32_t v = *reinterpret_cast<const uint32_t *>(
-                lat + (int64_t)(oy + row) * L + ox + 4 * c4);
-            *reinterpret_cast<uint32_t *>(tile + row * SB + 4 * c4) = v;
+        if ((nd & 15u) == 0) {
+            for (int q = lane; q < (int)(nd >> 4); q += 64)
+                *reinterpret_cast<uint4 *>(tile + 16 * q) =
+                    *reinterpret_cast<const uint4 *>(blk + 16 * q);
+        } else {
+            for (int q = lane; q < (int)(nd >> 2); q += 64)
+                *reinterpret_cast<uint32_t *>(tile + 4 * q) =
+                    *reinterpret_cast<const uint32_t *>(blk + 4 * q);
         }
         if (lane < 2 * B4 && !ring) {
             const int which = lane / B4, c4 = lane - which * B4;
-            const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
-            const uint32_t v =
-                *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + ox + 4 * c4);
-            *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) = v;
+            const int8_t *src = which ? dn_row : up_row;
+            *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) =
+                *reinterpret_cast<const uint32_t *>(src + 4 * c4);
         }
     } else {
         for (int q = lane; q < By * B; q += 64) {
             const int row = q / B, col = q - row * B;
-            tile[row * SB + col] = (uint8_t)lat[(int64_t)(oy + row) * L + ox + col];
+            tile[row * SB + col] = (uint8_t)blk[q];
         }
         for (int q = lane; q < 2 * B && !ring; q += 64) {
             const int which = q / B, col = q - which * B;
-            const int y = which ? (oy + By) % L : (oy - 1 + L) % L;
-            hrow[which * 64 + col] = (uint8_t)lat[(int64_t)y * L + ox + col];
+            hrow[which * 64 + col] = (uint8_t)(which ? dn_row : up_row)[col];
         }
     }
-    MT hl = 0, hr = 0;
-    if (lane < By) {
-        const int64_t rowbase = (int64_t)(oy + lane) * L;
-        hl = lat[rowbase + (ox - 1 + L) % L] > 0 ? 1 : 0;
-        hr = lat[rowbase + (ox + B) % L] > 0 ? 1 : 0;
-    }
+    // left halo: the left neighbour's last column; right: the right one's first
+    const uint64_t e_lf = edges[2 * d_lf + 1], e_rt = edges[2 * d_rt];
+    const MT hl = lane < By ? (MT)((e_lf >> lane) & 1u) : (MT)0;
+    const MT hr = lane < By ? (MT)((e_rt >> lane) & 1u) : (MT)0;
     wave_sync_lds();
 
     const MT vm_row = B == 8 * (int)sizeof(MT) ? ~(MT)0 : (((MT)1 << B) - 1);
@@ -1082,23 +1122,36 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         }
     }
 
-    // ---- write the tile back through LDS
+    // ---- write the tile back through LDS, and the domain's edge columns
     if (lane < By) {
         for (int q = 0; q < SB4; ++q)
             *reinterpret_cast<uint32_t *>(tile + lane * SB + 4 * q) =
                 bits_to_bytes((uint32_t)(S >> (4 * q)) & 0xFu);
     }
+    {
+        // S is clear in lanes >= By
+        const uint64_t first = __ballot((uint32_t)S & 1u);
+        const uint64_t last = __ballot((uint32_t)(S >> (B - 1)) & 1u);
+        if (lane == 0)
+            *reinterpret_cast<ulonglong2 *>(edges + 2 * dd) =
+                make_ulonglong2((unsigned long long)first, (unsigned long long)last);
+    }
     wave_sync_lds();
+    int8_t *wblk = lat + (int64_t)dd * (int)nd;
     if ((B & 3) == 0) {
-        for (int q = lane; q < By * B4; q += 64) {
-            const int row = q / B4, c4 = q - row * B4;
-            *reinterpret_cast<uint32_t *>(lat + (int64_t)(oy + row) * L + ox + 4 * c4) =
-                *reinterpret_cast<const uint32_t *>(tile + row * SB + 4 * c4);
+        if ((nd & 15u) == 0) {
+            for (int q = lane; q < (int)(nd >> 4); q += 64)
+                *reinterpret_cast<uint4 *>(wblk + 16 * q) =
+                    *reinterpret_cast<const uint4 *>(tile + 16 * q);
+        } else {
+            for (int q = lane; q < (int)(nd >> 2); q += 64)
+                *reinterpret_cast<uint32_t *>(wblk + 4 * q) =
+                    *reinterpret_cast<const uint32_t *>(tile + 4 * q);
         }
     } else {
         for (int q = lane; q < By * B; q += 64) {
             const int row = q / B, col = q - row * B;
-            lat[(int64_t)(oy + row) * L + ox + col] = (int8_t)tile[row * SB + col];
+            wblk[q] = (int8_t)tile[row * SB + col];
         }
     }
     wave_sync_lds();  // LDS reads of the write-back finish before reuse
@@ -1154,7 +1207,8 @@ __global__ __launch_bounds__(64) void k_phase(KParams K, int p) {
     colour_domain(rp, col, task - rp.task_off, &d, &oy, &ox);
     const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
-        (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+        (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d,
+        K.edges + 2 * (int64_t)rp.dom_off, lds);
     if (__lane_id() == 0) {
         if (o.events) {
             atomicAdd((unsigned long long *)&K.acc[rho].M, (unsigned long long)o.dM);
@@ -1264,7 +1318,8 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
     Dom *dm = K.dom + rp.dom_off + d;
     const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
         K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
-        (uint32_t)vis, w, (uint32_t)rho, K.seed, dm, lds);
+        (uint32_t)vis, w, (uint32_t)rho, K.seed, dm,
+        K.edges + 2 * (int64_t)rp.dom_off, lds);
     if (__lane_id() == 0) {
         // this domain's visits so far in sweep w (the palindrome's second
         // visit has vis = 1), published first: the visits waiting on it need
@@ -1453,7 +1508,8 @@ __device__ void run_replica(const KParams &K, int rho, int wave, int nw, int lan
                 colour_domain(rp, col, i2, &d, &oy, &ox);
                 const VisitOut o = visit_domain<MT, SCORE, WRAP, SLICE>(
                     K.spins + rp.spin_off, rp, K.rates + rho, oy, ox, (uint32_t)d,
-                    (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d, lds);
+                    (uint32_t)vis, w, (uint32_t)rho, K.seed, K.dom + rp.dom_off + d,
+        K.edges + 2 * (int64_t)rp.dom_off, lds);
                 dM += o.dM;
                 dB += o.dB;
                 ev += o.events;
@@ -1557,6 +1613,9 @@ __global__ __launch_bounds__(64 * kWavesPerPersistentGroup) void k_persistent(
 
 // ------------------------------------------------------------ init kernels
 
+// Random and all-up starts.  Site i of the row-major order (y = i / L,
+// x = i mod L) takes bit i of the INIT stream: call i / 128, word
+// (i / 32) mod 4, bit i mod 32.
 __global__ void k_init_spins(KParams K) {
     const int rho = blockIdx.y;
     const Rep rp = K.reps[rho];
@@ -1564,15 +1623,54 @@ __global__ void k_init_spins(KParams K) {
     const int64_t call = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (call * 128 >= N || rp.init == 2) return;
     int8_t *lat = K.spins + rp.spin_off;
-    if (rp.init == 1) {
-        for (int i = 0; i < 128 && call * 128 + i < N; ++i) lat[call * 128 + i] = 1;
-        return;
+    const int L = rp.L;
+    uint32_t v[4] = {~0u, ~0u, ~0u, ~0u};
+    if (rp.init != 1) {
+        const uint4 o = philox((uint32_t)call, kStreamInit << 24, 0u, (uint32_t)rho,
+                               (uint32_t)K.seed, (uint32_t)(K.seed >> 32));
+        v[0] = o.x;
+        v[1] = o.y;
+        v[2] = o.z;
+        v[3] = o.w;
     }
-    const uint4 o = philox((uint32_t)call, kStreamInit << 24, 0u, (uint32_t)rho,
-                           (uint32_t)K.seed, (uint32_t)(K.seed >> 32));
-    const uint32_t v[4] = {o.x, o.y, o.z, o.w};
-    for (int i = 0; i < 128 && call * 128 + i < N; ++i)
-        lat[call * 128 + i] = ((v[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+    for (int i = 0; i < 128 && call * 128 + i < N; ++i) {
+        const int64_t s = call * 128 + i;
+        const int y = (int)(s / L), x = (int)(s - (int64_t)y * L);
+        lat[site_offset(rp, y, x)] = ((v[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+    }
+}
+
+// Given starts and copies out: row-major `rm` <-> the replica's
+// domain-by-domain block (one thread per site, coalesced on the block).
+template <bool TO_BLOCK>
+__global__ __launch_bounds__(256) void k_spins_layout(KParams K, int rho, int8_t *rm) {
+    const Rep rp = K.reps[rho];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= lattice_sites(rp)) return;
+    const int64_t i = row_major_of(rp, j);
+    int8_t *lat = K.spins + rp.spin_off;
+    if (TO_BLOCK)
+        lat[j] = rm[i];
+    else
+        rm[i] = lat[j];
+}
+
+// Rebuild every domain's edge columns from the spins (before a run of the
+// staged visits): one thread per domain, bit r = row r.
+__global__ __launch_bounds__(256) void k_edges(KParams K) {
+    const int rho = blockIdx.y;
+    const Rep rp = K.reps[rho];
+    const int dd = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (dd >= rp.ND || rp.By > 64) return;
+    const int8_t *blk = K.spins + rp.spin_off + (int64_t)dd * (int)rp.nd;
+    uint64_t first = 0, last = 0;
+    for (int r = 0; r < rp.By; ++r) {
+        first |= (uint64_t)(blk[r * rp.B] > 0) << r;
+        last |= (uint64_t)(blk[r * rp.B + rp.B - 1] > 0) << r;
+    }
+    uint64_t *e = K.edges + 2 * ((int64_t)rp.dom_off + dd);
+    e[0] = first;
+    e[1] = last;
 }
 
 // M and B of the start lattice; one thread per site, int64 atomics.
@@ -1586,10 +1684,10 @@ __global__ __launch_bounds__(256) void k_init_obs(KParams K) {
     if (i < N) {
         const int8_t *lat = K.spins + rp.spin_off;
         const int y = (int)(i / L), x = (int)(i % L);
-        const int s = lat[i];
+        const int s = lat[site_offset(rp, y, x)];
         m = s;
-        b = s * lat[(int64_t)y * L + (x + 1) % L];  // right bond
-        if (rp.z == 4) b += s * lat[(int64_t)((y + 1) % L) * L + x];  // down bond
+        b = s * lat[site_offset(rp, y, (x + 1) % L)];  // right bond
+        if (rp.z == 4) b += s * lat[site_offset(rp, (y + 1) % L, x)];  // down bond
     }
     const uint32_t sm = wave_sum_u32((uint32_t)m);
     const uint32_t sb = wave_sum_u32((uint32_t)b);

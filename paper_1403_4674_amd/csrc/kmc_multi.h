@@ -115,40 +115,45 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
 
     // ---- stage the slot's tile and halo rows through LDS (rows padded to
     // whole dwords, stride SB; sides that are not multiples of 4 byte by byte)
+    // The lattice is held domain by domain (B x B tiles of B^2 bytes, rows in
+    // order): the tile is contiguous, a halo row is a row of the domain above
+    // or below, a halo column a column of the tile to the left or right.
     const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds + slot * kSlotLds;
     uint8_t *hrow = tile + 16 * 16;  // [0, 16): top, [16, 32): bottom
+    const int NT = L / B, n2 = B * B, dd = (int)A.d;
+    const int d_up = A.oy == 0 ? dd + (NT - 1) * NT : dd - NT;
+    const int d_dn = A.oy + B == L ? dd - (NT - 1) * NT : dd + NT;
+    const int d_lf = A.ox == 0 ? dd + NT - 1 : dd - 1;
+    const int d_rt = A.ox + B == L ? dd - (NT - 1) : dd + 1;
+    const int8_t *blk = lat + (int64_t)dd * n2;
+    const int8_t *up_row = lat + (int64_t)d_up * n2 + (B - 1) * B;
+    const int8_t *dn_row = lat + (int64_t)d_dn * n2;
     if (A.on) {
         if ((B & 3) == 0) {
-            for (int q = sl; q < B * B4; q += kSlotW) {
-                const int row = q / B4, c4 = q - row * B4;
-                *reinterpret_cast<uint32_t *>(tile + row * SB + 4 * c4) =
-                    *reinterpret_cast<const uint32_t *>(lat + (int64_t)(A.oy + row) * L +
-                                                        A.ox + 4 * c4);
-            }
+            for (int q = sl; q < B * B4; q += kSlotW)
+                *reinterpret_cast<uint32_t *>(tile + 4 * q) =
+                    *reinterpret_cast<const uint32_t *>(blk + 4 * q);
             if (sl < 2 * B4) {
                 const int which = sl / B4, c4 = sl - which * B4;
-                const int y = which ? (A.oy + B) % L : (A.oy - 1 + L) % L;
                 *reinterpret_cast<uint32_t *>(hrow + which * 16 + 4 * c4) =
-                    *reinterpret_cast<const uint32_t *>(lat + (int64_t)y * L + A.ox + 4 * c4);
+                    *reinterpret_cast<const uint32_t *>((which ? dn_row : up_row) + 4 * c4);
             }
         } else {
             for (int q = sl; q < B * B; q += kSlotW) {
                 const int row = q / B, col = q - row * B;
-                tile[row * SB + col] = (uint8_t)lat[(int64_t)(A.oy + row) * L + A.ox + col];
+                tile[row * SB + col] = (uint8_t)blk[q];
             }
             for (int q = sl; q < 2 * B; q += kSlotW) {
                 const int which = q / B, col = q - which * B;
-                const int y = which ? (A.oy + B) % L : (A.oy - 1 + L) % L;
-                hrow[which * 16 + col] = (uint8_t)lat[(int64_t)y * L + A.ox + col];
+                hrow[which * 16 + col] = (uint8_t)(which ? dn_row : up_row)[col];
             }
         }
     }
     uint32_t hl = 0, hr = 0;
     if (A.on && sl < B) {
-        const int64_t rowbase = (int64_t)(A.oy + sl) * L;
-        hl = lat[rowbase + (A.ox - 1 + L) % L] > 0 ? 1u : 0u;
-        hr = lat[rowbase + (A.ox + B) % L] > 0 ? 1u : 0u;
+        hl = lat[(int64_t)d_lf * n2 + sl * B + B - 1] > 0 ? 1u : 0u;
+        hr = lat[(int64_t)d_rt * n2 + sl * B] > 0 ? 1u : 0u;
     }
     wave_sync_lds();
 
@@ -373,17 +378,15 @@ __device__ VisitOut visit_multi(int8_t *__restrict__ spins, const Rep &rp,
     }
     wave_sync_lds();
     if (A.on) {
+        int8_t *wblk = lat + (int64_t)dd * n2;
         if ((B & 3) == 0) {
-            for (int q = sl; q < B * B4; q += kSlotW) {
-                const int row = q / B4, c4 = q - row * B4;
-                *reinterpret_cast<uint32_t *>(lat + (int64_t)(A.oy + row) * L + A.ox +
-                                              4 * c4) =
-                    *reinterpret_cast<const uint32_t *>(tile + row * SB + 4 * c4);
-            }
+            for (int q = sl; q < B * B4; q += kSlotW)
+                *reinterpret_cast<uint32_t *>(wblk + 4 * q) =
+                    *reinterpret_cast<const uint32_t *>(tile + 4 * q);
         } else {
             for (int q = sl; q < B * B; q += kSlotW) {
                 const int row = q / B, col = q - row * B;
-                lat[(int64_t)(A.oy + row) * L + A.ox + col] = (int8_t)tile[row * SB + col];
+                wblk[q] = (int8_t)tile[row * SB + col];
             }
         }
     }

@@ -281,7 +281,8 @@ __global__ __launch_bounds__(64 * kResMaxWaves) void k_resident(KParams K, int64
     const int64_t rec_every = K.ctl->rec_every, rec_base = K.ctl->rec_base;
 
     // ---- codes of the current lattice and the row counts of every domain
-    for (int i = tid; i < L * L; i += nthr) code[i] = lat[i] > 0 ? 0x80 : 0;
+    // (HBM holds the lattice domain by domain; LDS row-major)
+    for (int j = tid; j < L * L; j += nthr) code[row_major_of(rp, j)] = lat[j] > 0 ? 0x80 : 0;
     for (int i = tid; i < NTx * L * 4; i += nthr) reinterpret_cast<uint32_t *>(rowc)[i] = 0u;
     __syncthreads();
     for (int i = tid; i < L * L; i += nthr) {
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(64 * kResMaxWaves) void k_resident(KParams K, int64
     }
     if (wave == 0 && lane == 0) K.acc[rho] = acc;
     // ---- the lattice back to HBM
-    for (int i = tid; i < L * L; i += nthr) lat[i] = code[i] >= 5 ? (int8_t)1 : (int8_t)-1;
+    for (int j = tid; j < L * L; j += nthr)
+        lat[j] = code[row_major_of(rp, j)] >= 5 ? (int8_t)1 : (int8_t)-1;
 }
 
 }  // namespace kmcdev

@@ -16,7 +16,7 @@ def test_traffic_is_tied_to_the_kernel_source(monkeypatch):
     assert bench.workload_name(dict(L=1024, tile=32, steps_per_visit=1024, T=2.269)) == name
     t = bench.traffic_per_sweep(name)
     if bench.TRAFFIC["kernel_source_sha256"] == bench.kernel_source_sha():
-        assert t is not None and 2.0 < t / 2228224 < 6.0
+        assert t is not None and 0.5 < t / 2228224 < 1.3
     monkeypatch.setitem(bench.TRAFFIC, "kernel_source_sha256", "0" * 64)
     assert bench.traffic_per_sweep(name) is None
     assert bench.traffic_per_sweep("no such workload") is None
