@@ -1065,6 +1065,26 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                     for (size_t q = 0; q < grp.size(); ++q) it.rho[q] = grp[q];
                     wv.push_back(it);
                 }
+            // A launch lasts as long as its longest item: start the items
+            // whose busiest slot has the most work per sweep first.  (A
+            // group of four small replicas runs one replica per slot, so
+            // its length is one replica's whole sweep; a replica split over
+            // the slots of a wavefront or workgroup divides its sweep.)
+            auto chain = [&](const MItem &it) {
+                auto per_slot = [&](int rho, int slots) {
+                    const Rep &r = c->reps[rho];
+                    const int passes = (r.ND / 4 + slots - 1) / slots;
+                    return sweep_cost(r, c->desc[rho]) / r.ND * 4.0 * passes;
+                };
+                if (it.kind == 1) return per_slot(it.rho[0], kmcdev::kSlots * it.nw);
+                double m = 0.0;
+                for (int q = 0; q < kmcdev::kSlots; ++q)
+                    if (it.rho[q] >= 0) m = std::max(m, per_slot(it.rho[q], 1));
+                return m;
+            };
+            auto longer = [&](const MItem &a, const MItem &b) { return chain(a) > chain(b); };
+            std::stable_sort(wg.begin(), wg.end(), longer);
+            std::stable_sort(wv.begin(), wv.end(), longer);
             const int64_t m_waves = 4 * (int64_t)wg.size() + (int64_t)wv.size();
             c->m_items = wg;
             c->m_items.insert(c->m_items.end(), wv.begin(), wv.end());
