@@ -30,7 +30,8 @@
  *    thread-safe.  Calls that launch work are asynchronous on that stream
  *    unless stated otherwise.
  *  - Inputs are copied; outputs are caller-owned memory.
- *  - Lattices are row-major int8 with values +1 / -1.
+ *  - Lattices passed in and out are row-major int8 with values +1 / -1
+ *    (the device copy is held domain by domain, which no call exposes).
  */
 #ifndef KMC_H
 #define KMC_H
