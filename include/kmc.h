@@ -77,11 +77,13 @@ typedef enum { KMC_INIT_RANDOM = 0, KMC_INIT_ALL_UP = 1, KMC_INIT_GIVEN = 2 } km
 #define KMC_F_SCORE 0x40u      /* accumulate the likelihood-ratio score of
                                   every tick while the run proceeds (the
                                   backward call then only copies it out)      */
-#define KMC_F_FLOW 0x100u      /* phase-by-phase form, one launch per sweep: each
-                                  domain visit starts as soon as the visits of
-                                  its neighbouring domains that precede it in
-                                  the sweep (Eq. (schedule)) have finished, so
-                                  non-adjacent colours overlap; results equal
+#define KMC_F_FLOW 0x100u      /* phase-by-phase form as dataflow launches of
+                                  up to 64 sweeps: each domain visit starts as
+                                  soon as the visits of its neighbouring
+                                  domains that precede it in the sequential
+                                  order (Eq. (schedule)) have finished, so
+                                  non-adjacent colours and consecutive sweeps
+                                  overlap; results equal
                                   the phase launches bit for bit.  Not with
                                   KMC_F_PERSISTENT (KMC_EINVAL).  A wait that
                                   never ends is cut off and reported as

@@ -92,8 +92,8 @@ struct kmc_ctx {
     int64_t *d_done = nullptr;  // per-domain visit counters of the one-launch sweeps
     // per-sweep slots of a dataflow launch (allocated on first use)
     int64_t flow_max_polls = kmcdev::kFlowMaxPolls;  // bound of each dataflow wait
-    int64_t *d_flow_acc = nullptr;  // [kFlowMaxSweeps][n_rep][3]
-    double *d_flow_clk = nullptr;   // [kFlowMaxSweeps][n_dom][2]
+    int64_t *d_flow_acc = nullptr;  // [flow_window][n_rep][3]
+    double *d_flow_clk = nullptr;   // [flow_window][n_dom][2]
     bool graph_flow = false;    // the cached phase graph was captured with flow
     bool flow = false;          // phase-by-phase sweeps as one dataflow launch
     int32_t *d_task_rep = nullptr;
@@ -403,11 +403,19 @@ void launch_sweep(kmc_ctx *c, KParams K);
 // size of a dispatch is a 32-bit count of work-items).
 constexpr int64_t kMaxBlocks = ((int64_t)1 << 32) / 64 - 1;
 
+// Device memory the per-sweep clock snapshots of one dataflow launch may use.
+constexpr int64_t kFlowClockBytes = (int64_t)256 << 20;
+
 // Sweeps one dataflow launch may hold: kFlowMaxSweeps, fewer when the grid
-// of G sweeps x phases x tasks would not fit one dispatch (0: not even one).
+// of G sweeps x phases x tasks would not fit one dispatch (0: not even one)
+// or the domains' clock snapshots of G sweeps would exceed kFlowClockBytes
+// (at least one sweep).
 int flow_window(const kmc_ctx *c) {
     const int64_t per_sweep = (int64_t)c->n_phase * std::max(c->n_tasks32, c->n_tasks - c->n_tasks32);
-    return (int)std::min<int64_t>(kmcdev::kFlowMaxSweeps, kMaxBlocks / std::max<int64_t>(per_sweep, 1));
+    const int64_t by_grid = kMaxBlocks / std::max<int64_t>(per_sweep, 1);
+    const int64_t by_mem =
+        std::max<int64_t>(1, kFlowClockBytes / (16 * (int64_t)std::max(c->n_dom, 1)));
+    return (int)std::min<int64_t>({(int64_t)kmcdev::kFlowMaxSweeps, by_grid, by_mem});
 }
 
 unsigned flow_blocks(kmc_ctx *c, int G, int n_tasks) {
@@ -568,11 +576,9 @@ void launch_resident(kmc_ctx *c, KParams K, int64_t n_sweeps) {
 // (Each buffer is checked on its own: after a failed allocation the next
 // call allocates what is still missing.)
 void ensure_flow_slots(kmc_ctx *c) {
-    if (!c->d_flow_acc)
-        c->d_flow_acc = alloc_n<int64_t>(c, (int64_t)kmcdev::kFlowMaxSweeps * c->n_rep * 3);
-    if (!c->d_flow_clk)
-        c->d_flow_clk =
-            alloc_n<double>(c, (int64_t)kmcdev::kFlowMaxSweeps * std::max(c->n_dom, 1) * 2);
+    const int64_t G = std::max(flow_window(c), 1);
+    if (!c->d_flow_acc) c->d_flow_acc = alloc_n<int64_t>(c, G * c->n_rep * 3);
+    if (!c->d_flow_clk) c->d_flow_clk = alloc_n<double>(c, G * std::max(c->n_dom, 1) * 2);
 }
 
 void ensure_records(kmc_ctx *c, int64_t need) {

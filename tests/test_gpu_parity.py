@@ -286,33 +286,37 @@ def test_one_launch_sweeps_are_bit_identical(torch_cuda, oracle_lib, graph):
 
 
 def test_dataflow_windows_of_many_sweeps(torch_cuda, oracle_lib):
-    """Runs longer than one dataflow launch (64 sweeps): sweeps of a window
-    overlap, records every 7 sweeps straddle the window boundaries, and the
-    result still equals the phase launches bit for bit (records, lattices,
-    per-domain clocks); the fused score over the windows matches the phase
-    form's within the score tolerance."""
+    """Runs longer than one dataflow launch (kmc.FLOW_MAX_SWEEPS sweeps):
+    sweeps of a window overlap, records every 7 sweeps straddle the window
+    boundaries, and the result still equals the phase launches bit for bit
+    (records, lattices, per-domain clocks); the fused score over the windows
+    matches the phase form's within the score tolerance."""
+    G = kmc.FLOW_MAX_SWEEPS
     descs = FLOW_MIX[:4] + [FLOW_MIX[6]]
-    say("dataflow windows: 150 sweeps, records every 7")
+    n1 = 2 * G + 22
+    say(f"dataflow windows: {n1} sweeps, records every 7")
     a = kmc.Lattice(descs, 91)
     b = kmc.Lattice(descs, 91)
-    a.run(150, 7)
-    b.run(150, 7, kmc.F_FLOW | kmc.F_TIMING)
+    a.run(n1, 7)
+    b.run(n1, 7, kmc.F_FLOW | kmc.F_TIMING)
     ms, n = b.timing()
-    assert n == 3 and ms > 0  # 64 + 64 + 22 sweeps
+    assert n == 3 and ms > 0  # G + G + 22 sweeps
     assert np.array_equal(a.records(), b.records())
     for rho in range(len(descs)):
         assert np.array_equal(a.spins(rho), b.spins(rho)), rho
         for x, y in zip(a.domain_state(rho), b.domain_state(rho)):
             assert np.array_equal(x, y), rho
     o = oracle_for(oracle_lib, descs[2], 91, 2)
-    assert_records_equal(b.records()[2], o.run(150, 7), "oracle")
-    say("dataflow windows: fused score, 130 sweeps")
-    a.run(130, 10, kmc.F_SCORE)
-    b.run(130, 10, kmc.F_FLOW | kmc.F_SCORE)
-    sa, sb = a.score(13), b.score(13)
+    assert_records_equal(b.records()[2], o.run(n1, 7), "oracle")
+    n2 = G + 50
+    say(f"dataflow windows: fused score, {n2} sweeps")
+    a.run(n2, 10, kmc.F_SCORE)
+    b.run(n2, 10, kmc.F_FLOW | kmc.F_SCORE)
+    nb = -(-n2 // 10)
+    sa, sb = a.score(nb), b.score(nb)
     assert np.array_equal(a.records(), b.records())
     for rho, d in enumerate(descs):
-        _, _, sc, mag = oracle_score(oracle_lib, d, 91, rho, 130, 10, pre=150)
+        _, _, sc, mag = oracle_score(oracle_lib, d, 91, rho, n2, 10, pre=n1)
         assert_score_close(sa[rho], sc, mag, f"phase form {rho}")
         assert_score_close(sb[rho], sc, mag, f"dataflow form {rho}")
 
