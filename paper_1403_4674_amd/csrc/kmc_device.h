@@ -760,7 +760,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     // ---- stage the tile and the top/bottom halo rows through LDS.  LDS rows
     // are padded to whole dwords (stride SB).  With widths that are multiples
     // of 4 the LDS tile is the HBM tile byte for byte and moves in 16-byte
-    // (else 4-byte) pieces; other widths move byte by byte.
+    // (else 4-byte) pieces; other widths move byte by byte.  Every load of
+    // the visit (tile, halo rows, edge words, rate tables, domain record) is
+    // issued before the first one is waited for: one memory round trip
+    // instead of one per kind.
     const int SB = (B + 3) & ~3, SB4 = SB >> 2;
     uint8_t *tile = lds;
     uint8_t *hrow = lds + 64 * 64;  // [0, B): top halo, [64, 64 + B): bottom
@@ -770,22 +773,47 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     // the ring (one row of L sites) has no rows above and below: its domains
     // have no top and bottom halo, and those neighbours count as down
     const bool ring = rp.z == 2;
-    if ((B & 3) == 0) {
-        if ((nd & 15u) == 0) {
-            for (int q = lane; q < (int)(nd >> 4); q += 64)
-                *reinterpret_cast<uint4 *>(tile + 16 * q) =
-                    *reinterpret_cast<const uint4 *>(blk + 16 * q);
-        } else {
-            for (int q = lane; q < (int)(nd >> 2); q += 64)
-                *reinterpret_cast<uint32_t *>(tile + 4 * q) =
-                    *reinterpret_cast<const uint32_t *>(blk + 4 * q);
-        }
-        if (lane < 2 * B4 && !ring) {
-            const int which = lane / B4, c4 = lane - which * B4;
-            const int8_t *src = which ? dn_row : up_row;
-            *reinterpret_cast<uint32_t *>(hrow + which * 64 + 4 * c4) =
-                *reinterpret_cast<const uint32_t *>(src + 4 * c4);
-        }
+    const bool vec4 = (B & 3) == 0, vec16 = vec4 && (nd & 15u) == 0;
+    const int n16 = vec16 ? (int)(nd >> 4) : 0;  // at most 64 * 64 / 16 = 4 per lane
+    // (every lane of a row of pieces loads, the last lanes clamped to the
+    // last piece, so the loads carry no lane mask and nothing waits for them
+    // here)
+    const uint4 *blk16 = reinterpret_cast<const uint4 *>(blk);
+    uint4 tv0 = {0, 0, 0, 0}, tv1 = tv0, tv2 = tv0, tv3 = tv0;
+    if (n16 > 0) tv0 = blk16[min(lane, n16 - 1)];
+    if (n16 > 64) tv1 = blk16[min(lane + 64, n16 - 1)];
+    if (n16 > 128) tv2 = blk16[min(lane + 128, n16 - 1)];
+    if (n16 > 192) tv3 = blk16[min(lane + 192, n16 - 1)];
+    const bool hlane = vec4 && lane < 2 * B4 && !ring;
+    const int hwhich = hlane ? lane / B4 : 0, hc4 = hlane ? lane - hwhich * B4 : 0;
+    uint32_t hv = 0;
+    if (hlane) hv = *reinterpret_cast<const uint32_t *>((hwhich ? dn_row : up_row) + 4 * hc4);
+    // left halo: the left neighbour's last column; right: the right one's first
+    const uint64_t e_lf = edges[2 * d_lf + 1], e_rt = edges[2 * d_rt];
+    const double rd_lane = lane < 10 ? rt->rd[lane] : 0.0;
+    const double inv_lane = lane < 10 ? rt->inv_rd[lane] : 0.0;
+    double w_lane = 0.0;  // score: w_c in the class lanes (the other tables at the end)
+    if constexpr (SCORE) {
+        if (lane < 10) w_lane = rt->w[lane];
+    }
+    // the domain record (only this domain's visits write it), updated at the end
+    double dom_sum = 0.0, dom_comp = 0.0;
+    int64_t dom_ev = 0;
+    if (lane == 0) {
+        dom_sum = dom->clk_sum;
+        dom_comp = dom->clk_comp;
+        dom_ev = dom->events;
+    }
+    if (vec16) {
+        uint4 *tile16 = reinterpret_cast<uint4 *>(tile);
+        if (lane < n16) tile16[lane] = tv0;
+        if (lane + 64 < n16) tile16[lane + 64] = tv1;
+        if (lane + 128 < n16) tile16[lane + 128] = tv2;
+        if (lane + 192 < n16) tile16[lane + 192] = tv3;
+    } else if (vec4) {
+        for (int q = lane; q < (int)(nd >> 2); q += 64)
+            *reinterpret_cast<uint32_t *>(tile + 4 * q) =
+                *reinterpret_cast<const uint32_t *>(blk + 4 * q);
     } else {
         for (int q = lane; q < By * B; q += 64) {
             const int row = q / B, col = q - row * B;
@@ -796,8 +824,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             hrow[which * 64 + col] = (uint8_t)(which ? dn_row : up_row)[col];
         }
     }
-    // left halo: the left neighbour's last column; right: the right one's first
-    const uint64_t e_lf = edges[2 * d_lf + 1], e_rt = edges[2 * d_rt];
+    if (hlane) *reinterpret_cast<uint32_t *>(hrow + hwhich * 64 + 4 * hc4) = hv;
     const MT hl = lane < By ? (MT)((e_lf >> lane) & 1u) : (MT)0;
     const MT hr = lane < By ? (MT)((e_rt >> lane) & 1u) : (MT)0;
     wave_sync_lds();
@@ -832,17 +859,10 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
     }
     // Rate sums are integers below n_d 2^32 <= 2^44, held in doubles: every
     // sum, difference, product n_c * r_c and comparison below is exact.
-    const double rd_lane = lane < 10 ? rt->rd[lane] : 0.0;
-    const double inv_lane = lane < 10 ? rt->inv_rd[lane] : 0.0;
     const uint32_t lane3 = lane < 10 ? 3u * lane : 30u;  // tally field (30: always 0)
     double W = (double)n_lane * rd_lane;
     double Pinc = scan16_f64(W);
     double R = rdl_f64(Pinc, 9);
-
-    double w_lane = 0.0;  // score: w_c in the class lanes (the other tables at the end)
-    if constexpr (SCORE) {
-        if (lane < 10) w_lane = rt->w[lane];
-    }
 
     VisitOut out{0, 0, 0, 0.0, 0.0};
     uint32_t ev_lane = 0;                  // lanes 0..9: events of class c = lane
@@ -1109,7 +1129,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
         cs = wave_sum_f64(cs);
         cc = wave_sum_f64(cc);
         if (lane == 0) {
-            double ds = dom->clk_sum, dc = dom->clk_comp;
+            double ds = dom_sum, dc = dom_comp;
             if constexpr (SLICE) {
                 neumaier_add(ds, dc, rp.tau);  // the domain's clock: one slice
             } else {
@@ -1118,7 +1138,7 @@ __device__ VisitOut visit_domain(int8_t *__restrict__ lat, const Rep &rp,
             }
             dom->clk_sum = ds;
             dom->clk_comp = dc;
-            dom->events += out.events;
+            dom->events = dom_ev + out.events;
         }
     }
 
