@@ -232,7 +232,9 @@ kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_model,
 /* Creates a context holding n_rep replicas on the current HIP device and
  * initialises their lattices (Sec. 3: the paper's systems are periodic
  * square lattices with a given start configuration).
- *   d           host array of n_rep descriptors (copied)
+ *   d           host array of n_rep descriptors (copied);
+ *               1 <= n_rep <= 65535 (KMC_EUNSUPPORTED above: replicas index
+ *               the second dimension of the launch grids)
  *   seed        64-bit key of the counter-based generator; every random
  *               number is Philox4x32-10(key = seed, counter = (tick,
  *               domain | visit<<20 | stream<<24, sweep, replica))
