@@ -59,18 +59,18 @@ HBM_PEAK = 8.0e12
 # summaries in profiles/ name the commands).  Valid only for the kernel
 # source the counters were taken on (sha256 of kmc_device.h); null otherwise.
 TRAFFIC = {
-    "kernel_source_sha256": "fe73ada48ae3f4dc47edcb9b8f17a1d38858a1394ad771c5f9e338f26ffd1740",
+    "kernel_source_sha256": "482e767096c3119e22c6f942ecb0af759350806890c7a98a0a69a5d80dfba949",
     # workload -> (read bytes, WRITE_SIZE KiB) per sweep
     "per_sweep": {
         # profiles/k_flow_ising2d_L1024_tile32_plain.md
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (53882624 / 64, 80041.16 / 64),
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain_phased": (4 * 493.303 * 1024,
-                                                                       4 * 296.0),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (54356224 / 64, 80013.84 / 64),
+        # profiles/k_phase_ising2d_L1024_tile32_plain.md (four launches a sweep)
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain_phased": (4 * 506454.4, 4 * 296.0),
         # profiles/k_flow_ising2d_L1024_tile32_small_NI.md
-        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (52461440 / 64, 81016.91 / 64),
-        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (52229952 / 64, 79357.78 / 64),
+        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (51771584 / 64, 81075.97 / 64),
+        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (51032128 / 64, 79455.34 / 64),
         # profiles/k_flow_ising2d_L4096_tile64_quench.md
-        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (41741440 / 8, 138381.22 / 8),
+        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (41095936 / 8, 138389.69 / 8),
     },
 }
 
