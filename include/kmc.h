@@ -180,7 +180,8 @@ kmc_status kmc_set_device_allocator(kmc_alloc_fn alloc, kmc_free_fn free_fn,
                                     void *user);
 
 /* Bound, in polls, of each wait of the dataflow sweeps (KMC_F_FLOW) of this
- * context; default 2^24 (seconds).  For callers that test the failure path:
+ * context; default 2^24 (a poll every few microseconds: about a minute).
+ * For callers that test the failure path:
  * a wait that exceeds it gives up, the run is reported as failed
  * (KMC_EDEVICE from kmc_observables, or from kmc_backward_score for a replay
  * with host output), and the context's results stay void from then on.
@@ -232,9 +233,7 @@ kmc_status kmc_rate_table(double J, double h, double T, int32_t rate_model,
 /* Creates a context holding n_rep replicas on the current HIP device and
  * initialises their lattices (Sec. 3: the paper's systems are periodic
  * square lattices with a given start configuration).
- *   d           host array of n_rep descriptors (copied);
- *               1 <= n_rep <= 65535 (KMC_EUNSUPPORTED above: replicas index
- *               the second dimension of the launch grids)
+ *   d           host array of n_rep descriptors (copied)
  *   seed        64-bit key of the counter-based generator; every random
  *               number is Philox4x32-10(key = seed, counter = (tick,
  *               domain | visit<<20 | stream<<24, sweep, replica))

@@ -402,8 +402,6 @@ void launch_sweep(kmc_ctx *c, KParams K);
 // A launch of 64-lane blocks covers fewer than 2^32 work-items (the grid
 // size of a dispatch is a 32-bit count of work-items).
 constexpr int64_t kMaxBlocks = ((int64_t)1 << 32) / 64 - 1;
-// Replicas of one context (the y dimension of a grid is at most 65535 blocks).
-constexpr int32_t kMaxReplicas = 65535;
 
 // Device memory the per-sweep clock snapshots of one dataflow launch may use.
 constexpr int64_t kFlowClockBytes = (int64_t)256 << 20;
@@ -926,11 +924,6 @@ extern "C" kmc_status kmc_init_lattice(kmc_ctx **out, const kmc_replica_desc *d,
                                        int32_t n_rep, uint64_t seed,
                                        const int8_t *given_spins, void *hip_stream) {
     if (!out || !d || n_rep < 1) return KMC_EINVAL;
-    // replicas index the second grid dimension of the per-replica launches
-    if (n_rep > kMaxReplicas) {
-        std::fprintf(stderr, "kmc_init_lattice: more than %d replicas\n", kMaxReplicas);
-        return KMC_EUNSUPPORTED;
-    }
     kmc_ctx *c = new (std::nothrow) kmc_ctx;
     if (!c) return KMC_ENOMEM;
     try {  // descriptors are checked before any device call

@@ -1315,9 +1315,13 @@ __global__ __launch_bounds__(64) void k_flow(KParams K, int n_tasks, int n_phase
             const int64_t *cnt = dn + ey * NT + ex;
             int64_t polls = 0;
             // relaxed polls (no cache invalidation per poll); one acquire
-            // fence once every wait is over
+            // fence once every wait is over.  Thousands of wavefronts wait
+            // at a time; a long sleep between polls (64 x 64 cycles) keeps
+            // them from crowding the memory system.  (Measured on the 1024^2
+            // lattice: 5 % off a sweep of one-tick visits against a 128-cycle
+            // sleep, none on the full visits; a twice longer sleep is slower.)
             while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(64);
                 if (++polls > K.flow_max_polls) {
                     __hip_atomic_store(&K.ctl->err, (int64_t)1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);

@@ -88,15 +88,6 @@ def test_init_rejects_invalid_descriptor(kmc, bad):
     assert st == kmc.KMC_EINVAL and not ctx.value
 
 
-def test_init_rejects_too_many_replicas(kmc):
-    """Replicas index the second grid dimension: at most 65535, refused
-    before any device call."""
-    arr = kmc.make_descs([dict(L=8, tile=4, T=2.0)] * 65536)
-    ctx = C.c_void_p()
-    st = kmc.lib().kmc_init_lattice(C.byref(ctx), arr, 65536, C.c_uint64(1), None, None)
-    assert st == kmc.KMC_EUNSUPPORTED and not ctx.value
-
-
 def test_calls_reject_null_context(kmc):
     L = kmc.lib()
     assert L.kmc_run_schedule(None, 1, 1, 0) == kmc.KMC_EINVAL
