@@ -59,18 +59,18 @@ HBM_PEAK = 8.0e12
 # summaries in profiles/ name the commands).  Valid only for the kernel
 # source the counters were taken on (sha256 of kmc_device.h); null otherwise.
 TRAFFIC = {
-    "kernel_source_sha256": "482e767096c3119e22c6f942ecb0af759350806890c7a98a0a69a5d80dfba949",
+    "kernel_source_sha256": "54005e3957125d9388ec63381d784c3c2ca20ef3715e67e9a16601db389259cc",
     # workload -> (read bytes, WRITE_SIZE KiB) per sweep
     "per_sweep": {
         # profiles/k_flow_ising2d_L1024_tile32_plain.md
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (54356224 / 64, 80013.84 / 64),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain": (52562560 / 64, 79994.09 / 64),
         # profiles/k_phase_ising2d_L1024_tile32_plain.md (four launches a sweep)
-        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain_phased": (4 * 506454.4, 4 * 296.0),
+        "ising2d_L1024_tile32_NI1024_T2.269_metropolis_plain_phased": (4 * 506444.8, 4 * 296.0),
         # profiles/k_flow_ising2d_L1024_tile32_small_NI.md
-        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (51771584 / 64, 81075.97 / 64),
-        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (51032128 / 64, 79455.34 / 64),
+        "ising2d_L1024_tile32_NI10_T2.269_metropolis_plain": (49081408 / 64, 81076.78 / 64),
+        "ising2d_L1024_tile32_NI1_T2.269_metropolis_plain": (48429056 / 64, 79422.59 / 64),
         # profiles/k_flow_ising2d_L4096_tile64_quench.md
-        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (41095936 / 8, 138389.69 / 8),
+        "ising2d_L4096_tile64_NI4096_T1.5_metropolis_plain": (40673024 / 8, 138348.72 / 8),
     },
 }
 
