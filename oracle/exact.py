@@ -237,6 +237,50 @@ class RingTickKernel:
         return v
 
 
+def tick_at(p, states, sites, neighbours, J, h, T, model=0, quantise=False):
+    """p' at the given states after one tick of the domain `sites` applied to
+    the full vector p (Eq. (Glauber_TM): site i of the n_d sites is chosen with
+    probability 1/n_d and flipped with probability w_i), for systems whose
+    2^N x N tables TickKernel cannot hold:
+
+        p'(s) = p(s) - sum_i q_i(s) p(s) + sum_i q_i(s ^ 2^i) p(s ^ 2^i),
+
+    q_i(s) = w(dE_i(s)) / n_d, dE_i = 2 s_i (J sum of the neighbours' spins + h).
+    neighbours(i) lists the sites bonded to i, a site met twice counted twice
+    (the two neighbours along an axis of length 2)."""
+    states = np.asarray(states, dtype=np.int64)
+    nd = len(sites)
+
+    def q(s, i):
+        spin = lambda j: 2.0 * ((s >> j) & 1) - 1.0
+        n = sum(spin(j) for j in neighbours(i))
+        w = rate(2.0 * spin(i) * (J * n + h), T, model)
+        if quantise:
+            w = np.minimum(np.floor(w * 2.0 ** 32 + 0.5), 2.0 ** 32) / 2.0 ** 32
+        return w / nd
+
+    out = p[states].copy()
+    for i in sites:
+        partner = states ^ (1 << i)
+        out -= q(states, i) * p[states]
+        out += q(partner, i) * p[partner]
+    return out
+
+
+def square_neighbours(L):
+    """The four bonded sites of site i = y L + x on the periodic L x L lattice."""
+    def nb(i):
+        y, x = divmod(i, L)
+        return [((y - 1) % L) * L + x, ((y + 1) % L) * L + x,
+                y * L + (x - 1) % L, y * L + (x + 1) % L]
+    return nb
+
+
+def ring_neighbours(N):
+    """The two bonded sites of site i on the periodic ring of N sites."""
+    return lambda i: [(i - 1) % N, (i + 1) % N]
+
+
 def ring_partition(N, B):
     """Domains of B consecutive sites, their colours along the ring (one
     colour for one domain, t mod 2 for an even count, t mod 2 with the last
