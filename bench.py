@@ -21,6 +21,9 @@ Extra legs on the same line (none of them part of `value`):
   and the HBM roofline is the one that applies;
 * batched: the persistent form on 4096 ragged replicas;
 * backward: the score replay and the fused score on 1024 replicas of 64x64;
+* exact_5x5: exact propagation of the distribution over the 2^25
+  configurations of a 5x5 lattice (the verification tool), against the HBM
+  roofline;
 * parity: the timed plain form and the batched multi-slot form against the
   oracle;
 * cpu_baseline / cpu_batched: the serial CPU oracle on bounded samples.
@@ -75,9 +78,19 @@ TRAFFIC = {
 }
 
 
-def kernel_source_sha():
+# The same for one tick of exact propagation on the 5 x 5 lattice (both
+# passes; profiles/k_exact_tick_L5_one_domain.md), valid for the kernel
+# source of kmc_exact.h it was taken on.
+EXACT_TRAFFIC = {
+    "kernel_source_sha256": "aae916c7b50745228cfb0b7812950f88fdb570f5100354d9bb24cdc4deb413b6",
+    # (read bytes, WRITE_SIZE KiB) per tick: k_exact_hi + k_exact_lo
+    "per_tick": (268875039 + 536952160, 314743.63 + 262144.08),
+}
+
+
+def kernel_source_sha(name="kmc_device.h"):
     import hashlib
-    src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", "kmc_device.h")
+    src = os.path.join(ROOT, "paper_1403_4674_amd", "csrc", name)
     with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
@@ -189,6 +202,43 @@ def leg(p, extra=None):
            "workload": p["workload"], "roofline": roofline(p)}
     out.update(extra or {})
     return out
+
+
+def exact(kmc, sweeps=2, L=5):
+    """Exact propagation of the distribution over the 2^(L^2) configurations
+    of an L x L lattice (one domain of L^2 sites, N_I = L^2 ticks a sweep)
+    through `sweeps` sweeps (the verification tool, Sec. 3.1).  A tick is two
+    launches over tiles of 2^14 states in LDS (k_exact_hi: the states that
+    share bits 3..13; k_exact_lo: consecutive states), algorithmically a
+    read of the 2^N doubles and a write of 2^N (every flip partner is an
+    entry of the same vector); the two passes move 40 bytes a state (p twice,
+    the partial sums written and read, p' written).  HBM roofline over the
+    timed sweeps (the last tick of a sweep writes p itself)."""
+    import torch
+    N = L * L
+    n = 1 << N
+    d = dict(L=L, tile=L, T=2.5, h=0.1)
+    p = torch.zeros(n, dtype=torch.float64, device="cuda")
+    p[0] = 1.0
+    work = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    kmc.kmc_exact_sweeps(d, p, work, 1)  # warm-up
+    stream = torch.cuda.current_stream()
+    sec = timed(lambda: kmc.kmc_exact_sweeps(d, p, work, sweeps), stream)
+    total = float(p.sum().item())
+    ticks = sweeps * N
+    alg = ticks * 2 * 8 * n
+    traffic = None
+    if L == 5 and EXACT_TRAFFIC["kernel_source_sha256"] == kernel_source_sha("kmc_exact.h"):
+        read, write_kib = EXACT_TRAFFIC["per_tick"]
+        traffic = read + write_kib * 1024.0
+    return {"value": ticks * n / sec, "unit": "state-ticks/s", "sweeps": sweeps,
+            "states": n, "ticks": ticks, "ms_per_sweep": sec * 1e3 / sweeps,
+            "probability_sum": total, "workload": f"exact_L{L}_one_domain_NI{N}",
+            "roofline": {"bound": "hbm", "kernel": "k_exact_lo + k_exact_hi (one tick)",
+                         "achieved": alg / sec / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": alg / sec / HBM_PEAK, "algorithmic_bytes_per_tick": 16 * n,
+                         "traffic": traffic, "traffic_unit": "bytes_per_tick",
+                         "timing": "timed_region_over_the_sweeps"}}
 
 
 def parse_tiles(text):
@@ -372,9 +422,10 @@ def main():
                          "launches of up to 64 sweeps, KMC_F_FLOW)")
     ap.add_argument("--batched-sweeps", type=int, default=40)
     ap.add_argument("--grad-sweeps", type=int, default=200)
+    ap.add_argument("--exact-sweeps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mode", default="all",
-                    choices=["all", "plain", "small_ni", "quench", "batched", "backward",
+                    choices=["all", "plain", "small_ni", "quench", "batched", "backward", "exact",
                              "copy"],
                     help="all: the full line; the others run one part (for profiling)")
     ap.add_argument("--ni", type=int, default=0,
@@ -425,6 +476,9 @@ def main():
         for ni in ([args.ni] if args.ni else SMALL_NI):
             p = plain(args, kmc, small_ni_desc(d, ni), sd, args.steps, args.warmup)
             print(json.dumps({f"NI{ni}": leg(p)}), flush=True)
+        return
+    if args.mode == "exact":
+        print(json.dumps({"exact_5x5": exact(kmc, args.exact_sweeps)}), flush=True)
         return
     if args.mode == "quench":
         seed3, d3s, _ = workloads.quench_4096()
@@ -492,6 +546,7 @@ def main():
         # sweep for the same dependency depth of the schedule
         line["small_NI"]["NI10_L4096"] = leg(
             plain(args, kmc, small_ni_desc(d3s[0], 10), seed3, 64, 16))
+        line["exact_5x5"] = exact(kmc, args.exact_sweeps)
         b = batched(args, kmc, workloads)
         g = backward(args, kmc, workloads)
         b_ops = OPS_PER_TICK * b["ticks"] + OPS_PER_EVENT * b["events"]

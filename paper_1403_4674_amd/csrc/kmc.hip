@@ -751,6 +751,7 @@ namespace {
 struct ExactPlan {
     kmcdev::ExactDomain dom[kmcdev::kExactMaxSites];
     int col[kmcdev::kExactMaxSites];
+    bool two_pass[kmcdev::kExactMaxSites];  // a site at state bit 14 or above
     int n_dom = 0;
     int orders[24][18];
     int n_orders = 0, order_len = 0;
@@ -788,13 +789,46 @@ kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, 
                 for (int lx = 0; lx < Bx; ++lx) {
                     const int a = ly * Bx + lx, y = ty * By + ly, x = tx * Bx + lx;
                     D.site[a] = y * L + x;
-                    // on the ring the up and down neighbours are bit N of the
-                    // state index, which is 0 for every state: never up
-                    D.nb[a][0] = ring ? N : ((y + L - 1) % L) * L + x;
-                    D.nb[a][1] = ring ? N : ((y + 1) % L) * L + x;
-                    D.nb[a][2] = y * L + (x + L - 1) % L;
-                    D.nb[a][3] = y * L + (x + 1) % L;
+                    // the ring has no up and down neighbours; on a side of 2
+                    // the two neighbours along an axis are one site, counted
+                    // twice
+                    int nb[4] = {y * L + (x + L - 1) % L, y * L + (x + 1) % L, -1, -1};
+                    if (!ring) {
+                        nb[2] = ((y + L - 1) % L) * L + x;
+                        nb[3] = ((y + 1) % L) * L + x;
+                    }
+                    for (int q = 0; q < 4; ++q) {
+                        if (nb[q] < 0) continue;
+                        const uint32_t bit = 1u << nb[q];
+                        if (D.nb1[a] & bit)
+                            D.nb2[a] |= bit;
+                        else
+                            D.nb1[a] |= bit;
+                    }
                 }
+            P.two_pass[P.n_dom] = false;
+            for (int a = 0; a < D.n; ++a) {
+                P.two_pass[P.n_dom] |= D.site[a] >= kmcdev::kExactLoBits;
+                // state j of a thread differs from its state 0 in the bits
+                // J_j (contiguous pass: j << 9; strided pass: tile bits
+                // 10..13 of j placed as the pass spreads them); its class
+                // moves by the neighbours and the site itself among them
+                const int c = kmcdev::kExactHiBits + kmcdev::kExactLoBits - N;
+                for (int j = 0; j < kmcdev::kExactPerThread; ++j) {
+                    const uint32_t l = (uint32_t)j << (kmcdev::kExactLoBits - 4);
+                    const uint32_t lh = (uint32_t)j << (kmcdev::kExactHiBits - 4);
+                    uint32_t Jh = 0;
+                    if (N > kmcdev::kExactLoBits)
+                        Jh = (lh & ((1u << c) - 1u)) | ((lh >> c) << kmcdev::kExactLoBits);
+                    auto delta = [&](uint32_t J) {
+                        return (uint64_t)(__builtin_popcount(J & D.nb1[a]) +
+                                          __builtin_popcount(J & D.nb2[a]) +
+                                          (((J >> D.site[a]) & 1u) << 3));
+                    };
+                    D.dlo[a] |= delta(l) << (4 * j);
+                    D.dhi[a] |= delta(Jh) << (4 * j);
+                }
+            }
             P.col[P.n_dom++] = axis_colour(tx, NTx) + cx * axis_colour(ty, NTy);
         }
     // colour orders: all of them (mixed uniformly) or the palindrome
@@ -822,29 +856,61 @@ kmc_status exact_plan(const kmc_replica_desc *d, uint32_t flags, int max_sites, 
 
 // Enqueues n_sweeps sweeps of the plan on st: p in and out, work holds three
 // vectors of 2^N doubles (the mixture's accumulator and two tick buffers);
-// every entry of work is written before it is read.
+// every entry of work is written before it is read.  An order's first tick
+// reads p itself.  With one order its last tick writes p (in place when it
+// is also the first: each tile of a tick pass is read whole before any of it
+// is written, and no other workgroup reads it); with several the orders'
+// results are mixed in the accumulator.
 void exact_enqueue(const ExactPlan &P, int N, double *p, double *work, int64_t n_sweeps,
                    hipStream_t st) {
     const int64_t n = (int64_t)1 << N;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    const unsigned lo_tiles = N >= kmcdev::kExactLoBits ? 1u << (N - kmcdev::kExactLoBits) : 1u;
+    const unsigned hi_tiles = N > kmcdev::kExactHiBits ? 1u << (N - kmcdev::kExactHiBits) : 1u;
     double *acc = work, *b0 = work + n, *b1 = work + 2 * n;
+    auto tick = [&](int i, const double *in, double *out, double *part) {
+        if (N < kmcdev::kExactLoBits) {
+            hipLaunchKernelGGL(kmcdev::k_exact_small, dim3(1), dim3(1024), 0, st, in, out, N,
+                               P.dom[i], P.R, P.inv_nd);
+        } else if (!P.two_pass[i]) {
+            hipLaunchKernelGGL(kmcdev::k_exact_lo<false>, dim3(lo_tiles),
+                               dim3(kmcdev::kExactLoBlock), 0, st, in, nullptr, out, N, P.dom[i],
+                               P.R, P.inv_nd);
+        } else {  // part holds the high sites' terms between the passes
+            hipLaunchKernelGGL(kmcdev::k_exact_hi, dim3(hi_tiles), dim3(kmcdev::kExactHiBlock),
+                               0, st, in, part, N, P.dom[i], P.R);
+            hipLaunchKernelGGL(kmcdev::k_exact_lo<true>, dim3(lo_tiles),
+                               dim3(kmcdev::kExactLoBlock), 0, st, in, part, out, N, P.dom[i],
+                               P.R, P.inv_nd);
+        }
+    };
+    // the domains of one order, visit by visit
+    int seq[2 * kmcdev::kExactMaxSites];
     for (int64_t sw = 0; sw < n_sweeps; ++sw) {
         for (int k = 0; k < P.n_orders; ++k) {
-            double *cur = b0, *nxt = b1;
-            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, p, cur, n);
+            int n_seq = 0;
             for (int q = 0; q < P.order_len; ++q)
-                for (int i = 0; i < P.n_dom; ++i) {
-                    if (P.col[i] != P.orders[k][q]) continue;
-                    for (int t = 0; t < P.NI; ++t) {
-                        hipLaunchKernelGGL(kmcdev::k_exact_tick, dim3(grid), dim3(256), 0, st,
-                                           cur, nxt, n, P.dom[i], P.R, P.inv_nd);
-                        std::swap(cur, nxt);
-                    }
+                for (int i = 0; i < P.n_dom; ++i)
+                    if (P.col[i] == P.orders[k][q]) seq[n_seq++] = i;
+            const int n_ticks = n_seq * P.NI;
+            const double *cur = p;
+            double *nxt = b0;
+            for (int v = 0, tk = 0; v < n_seq; ++v)
+                for (int t = 0; t < P.NI; ++t, ++tk) {
+                    const bool last = tk == n_ticks - 1 && P.n_orders == 1;
+                    double *out = last ? p : nxt;
+                    // the high sites' terms: out itself, or any vector but cur
+                    double *part = out != p ? out : (cur == b0 ? b1 : b0);
+                    tick(seq[v], cur, out, part);
+                    cur = out;
+                    nxt = nxt == b0 ? b1 : b0;
                 }
-            hipLaunchKernelGGL(kmcdev::k_exact_axpy, dim3(grid), dim3(256), 0, st, acc, cur,
-                               1.0 / (double)P.n_orders, n, k == 0 ? 1 : 0);
+            if (P.n_orders > 1)
+                hipLaunchKernelGGL(kmcdev::k_exact_axpy, dim3(grid), dim3(256), 0, st, acc, cur,
+                                   1.0 / (double)P.n_orders, n, k == 0 ? 1 : 0);
         }
-        hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, acc, p, n);
+        if (P.n_orders > 1)
+            hipLaunchKernelGGL(kmcdev::k_exact_copy, dim3(grid), dim3(256), 0, st, acc, p, n);
     }
 }
 

@@ -20,3 +20,13 @@ def test_traffic_is_tied_to_the_kernel_source(monkeypatch):
     monkeypatch.setitem(bench.TRAFFIC, "kernel_source_sha256", "0" * 64)
     assert bench.traffic_per_sweep(name) is None
     assert bench.traffic_per_sweep("no such workload") is None
+
+
+def test_exact_traffic_constant():
+    # the two tick passes move 40 bytes a state against the 16 of one read
+    # and one write of the 2^25 doubles; the constant names the source of
+    # kmc_exact.h it was taken on (the benchmark reports null for another)
+    read, write_kib = bench.EXACT_TRAFFIC["per_tick"]
+    ratio = (read + write_kib * 1024.0) / (16 << 25)
+    assert 2.0 < ratio < 3.0
+    assert len(bench.EXACT_TRAFFIC["kernel_source_sha256"]) == 64

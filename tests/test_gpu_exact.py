@@ -12,6 +12,14 @@ needs an MI355X).
   replicas of a 4 x 4 lattice run by the batched persistent kernel after two
   sweeps from the all-up start matches the exact (quantised) distribution
   (chi-square).
+* Large systems, where a tick runs as two passes over tiles in LDS (one over
+  runs of 2^(28 - N) consecutive states, one over 2^14 consecutive states):
+  rings of 20 and 22 sites (one domain; two domains and two colour orders),
+  of 13 and 14 (one tile, one pass) and of 15 (three domains, six orders,
+  two tiles of the strided pass) equal to the numpy tool over the whole
+  vector; one tick of the 5 x 5 lattice (2^25 states) and of the 24-
+  and 26-site rings (2^26, the largest system) equal to the oracle's value
+  at 4096 sampled states and their flip partners.
 """
 import numpy as np
 import pytest
@@ -140,3 +148,42 @@ def test_kmc_histogram_matches_exact_distribution(torch_cuda):
     obs = np.append(counts[big], counts[~big].sum())
     ex = np.append(exp_[big], exp_[~big].sum())
     assert stats.chisquare(obs, ex * obs.sum() / ex.sum()).pvalue > 1e-5
+
+
+@pytest.mark.parametrize("N,B,NI", [(13, 13, 2), (14, 7, 1), (15, 5, 1), (20, 20, 2),
+                                      (22, 11, 2)])
+def test_two_pass_ticks_equal_the_ring_tool(torch_cuda, N, B, NI):
+    d = dict(L=N, tile=B, T=2.0, h=0.15, rate_model=kmc.RATE_BARKER, steps_per_visit=NI,
+             dims=1)
+    rng = np.random.default_rng(N)
+    p0 = rng.random(1 << N)
+    p0 /= p0.sum()
+    op = exact.RingSweepOperator(N, B, 1.0, 0.15, 2.0, 1, NI, quantise=True)
+    ref = op.par(p0)
+    say(f"exact propagation, ring of {N}, domains of {B}, N_I={NI}")
+    got = gpu_exact(torch_cuda, d, p0, 1, quantised=True)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("system", ["square 5x5", "ring 24", "ring 26"])
+def test_one_tick_of_the_largest_systems_at_sampled_states(torch_cuda, system):
+    if system == "square 5x5":
+        N, d = 25, dict(L=5, tile=5, T=2.3, h=0.1, steps_per_visit=1)
+        nb = exact.square_neighbours(5)
+        J, h, T, model = 1.0, 0.1, 2.3, 0
+    else:
+        N = int(system.split()[1])
+        d = dict(L=N, tile=N, T=2.0, h=-0.1, steps_per_visit=1, dims=1,
+                 rate_model=kmc.RATE_BARKER)
+        nb = exact.ring_neighbours(N)
+        J, h, T, model = 1.0, -0.1, 2.0, 1
+    rng = np.random.default_rng(N)
+    p0 = rng.random(1 << N)
+    p0 /= p0.sum()
+    say(f"one exact tick of the {system} lattice, 2^{N} states")
+    got = gpu_exact(torch_cuda, d, p0, 1, quantised=False)
+    s = rng.integers(0, 1 << N, 4096)
+    s = np.concatenate([s, s ^ (1 << rng.integers(0, N, s.size)), [0, (1 << N) - 1]])
+    ref = exact.tick_at(p0, s, list(range(N)), nb, J, h, T, model)
+    np.testing.assert_allclose(got[s], ref, rtol=1e-12, atol=0)
+    assert abs(got.sum() - 1.0) < 1e-12
