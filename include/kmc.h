@@ -190,13 +190,14 @@ kmc_status kmc_set_wait_limit(kmc_ctx *c, int64_t max_polls);
 
 /* Exact propagation (Sec. 3.1: reference values from evolving the
  * probability vector with Eq. (CK_parallel in s)) of one replica's
- * distribution over all 2^(L*L) spin configurations through n_sweeps sweeps
- * of the parallel transition matrix T_PAR: the uniform mixture over all
- * orders of the colours (Eq. (sum of sequential tms); at most 4 colours,
- * else KMC_EUNSUPPORTED), or the palindrome.  State index s: bit y*L + x set
- * when spin (y, x) is +1.  p: device array of 2^(L*L) doubles, the start
- * distribution in, the result out; work: device array of 3 * 2^(L*L)
- * doubles (caller-owned scratch; the call allocates nothing).  L*L <= 26;
+ * distribution over all 2^N spin configurations (N = L*L, or L for a ring)
+ * through n_sweeps sweeps of the parallel transition matrix T_PAR: the
+ * uniform mixture over all orders of the colours (Eq. (sum of sequential
+ * tms); at most 4 colours, else KMC_EUNSUPPORTED), or the palindrome.  State
+ * index s: bit y*L + x set when spin (y, x) is +1.  p: device array of 2^N
+ * doubles, the start distribution in, the result out; work: device array of
+ * 3 * 2^N doubles (caller-owned scratch; the call allocates nothing).  p and
+ * work must not overlap.  N <= 26, else KMC_EINVAL;
  * the descriptor's init and seed play no part.  Flags: KMC_EXACT_QUANTISED
  * uses the Q32 rates the kMC path flips with (else the real w).  Enqueued on
  * hip_stream (NULL: the null stream); asynchronous.  A verification tool:
@@ -209,8 +210,8 @@ kmc_status kmc_exact_sweeps(const kmc_replica_desc *d, double *p, double *work,
  * workspace (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the same propagation, with the three work vectors
  * in a buffer inside the library, 3 * 2^16 doubles (1.5 MiB), which every
- * device the library runs on holds until the process ends.  So L*L <= 16:
- * larger lattices return KMC_EINVAL before anything is enqueued.  p, flags,
+ * device the library runs on holds until the process ends.  So N <= 16:
+ * larger systems return KMC_EINVAL before anything is enqueued.  p, flags,
  * hip_stream and the errors are those of kmc_exact_sweeps; the call
  * allocates nothing.  Every call on one device shares that device's buffer:
  * calls whose work overlaps on one device (on different streams, or from
