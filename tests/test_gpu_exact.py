@@ -6,8 +6,9 @@ needs an MI355X).
   and without the Q32 rate quantisation.
 * At 5 x 5 (2^25 states, beyond what the numpy tool reaches in seconds):
   probability is conserved and the Boltzmann distribution is stationary
-  (Eq. (general reversibility condition)) for the unpartitioned lattice and
-  for the 25 one-site domains (9 colours, palindrome).
+  (Eq. (general reversibility condition)) for the unpartitioned lattice, for
+  the 25 one-site domains (9 colours, palindrome) and for five horizontal
+  stripes (3 colours mixed over their 6 orders).
 * The kMC path at scale against it: the joint (M, B) histogram of 200 000
   replicas of a 4 x 4 lattice run by the batched persistent kernel after two
   sweeps from the all-up start matches the exact (quantised) distribution
@@ -104,6 +105,9 @@ def boltzmann_gpu(torch, L, J, h, T):
     dict(L=5, tile=5, T=2.3, h=0.1, steps_per_visit=25),
     dict(L=5, tile=1, T=2.6, h=-0.05, steps_per_visit=1, schedule=kmc.SCHED_PALINDROME,
          rate_model=kmc.RATE_BARKER),
+    # five horizontal stripes, three colours mixed over their six orders;
+    # the stripes below site 14 tick in one pass, the others in two
+    dict(L=5, tile=5, tile_rows=1, T=2.4, h=0.05, steps_per_visit=3),
 ])
 def test_boltzmann_is_stationary_at_5x5(torch_cuda, d):
     torch = torch_cuda
